@@ -1,0 +1,183 @@
+/*
+ * tc.h -- exact 16-class directed triad census on AMD MI355X (gfx950).
+ *
+ * The problem (Nagpal 2013, section "Triad Census Algorithm"): a strict digraph
+ * G = [V, E], V = {0 .. n-1}, E a set of ordered pairs, goes in; the census
+ * array with the frequency of each of the 16 isomorphic triad types comes out.
+ * Classes are indexed 0..15 in the thesis's numbering (types 1..16):
+ *   0 003, 1 012, 2 102, 3 021D, 4 021U, 5 021C, 6 111D, 7 111U,
+ *   8 030T, 9 030C, 10 201, 11 120D, 12 120U, 13 120C, 14 210, 15 300.
+ * The counts sum to C(n,3).  The census is computed by the subquadratic
+ * dyad-based method (figure "Subquadratic Triad Census Algorithm"), one task per
+ * canonical dyad (connected pair u < v), on the GPU; every count is exact.
+ *
+ * Conventions for every function:
+ *   - returns TC_OK (0) or a negative TC_ERR_* code; no exception crosses the ABI;
+ *   - on error, caller-visible outputs are left untouched;
+ *   - pointers documented as host pointers must be host memory; device
+ *     pointers (TC_BUILD_DEVICE_PTRS) must be allocated on the context's device;
+ *   - a tc_context owns one HIP stream (its own or the caller's) on one device;
+ *     calls on one context are serialised internally and may come from any thread.
+ */
+#ifndef TC_H
+#define TC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tc_context_s* tc_context;
+typedef struct tc_graph_s* tc_graph;
+typedef uint64_t tc_ticket;
+
+enum {
+    TC_OK = 0,
+    TC_ERR_ARG = -1,       /* bad argument: null pointer, id outside [0, n), strict-mode violation */
+    TC_ERR_RANGE = -2,     /* n > 4,801,280 (C(n,3) would not fit uint64) or > 2^32 neighbour entries */
+    TC_ERR_NOMEM = -3,     /* device or host allocation failed, or the job exceeds the HBM budget */
+    TC_ERR_DEVICE = -4,    /* a HIP call failed */
+    TC_ERR_BUSY = -5,      /* graph still referenced by pending tickets */
+    TC_ERR_NOT_FOUND = -6, /* unknown ticket */
+    TC_ERR_SHUTDOWN = -7   /* context is shutting down; ticket cancelled */
+};
+
+enum {
+    TC_BUILD_DEFAULT = 0,     /* drop loops (u,u) and merge repeated arcs */
+    TC_BUILD_STRICT = 1,      /* reject loops and repeated arcs with TC_ERR_ARG */
+    TC_BUILD_DEVICE_PTRS = 2  /* src/dst are device pointers (e.g. torch tensors) */
+};
+
+enum { TC_NUM_CLASSES = 16, TC_NUM_BUCKETS = 3 };
+
+/* What the build kept and how the canonical dyads were bucketed. */
+typedef struct {
+    int64_t arcs_in;              /* m as passed */
+    int64_t arcs_kept;            /* distinct arcs after dropping loops and repeats */
+    int64_t self_loops_dropped;
+    int64_t duplicates_dropped;
+    int64_t asym_dyads;           /* canonical dyads joined one way */
+    int64_t mutual_dyads;         /* canonical dyads joined both ways */
+    int64_t max_degree;           /* max |N(u)| (undirected) */
+    uint64_t device_bytes;        /* HBM held by the resident graph */
+    uint64_t sum_d2;              /* sum over u of |N(u)|^2 = sum over dyads of |N(u)|+|N(v)| */
+    uint64_t bucket_dyads[TC_NUM_BUCKETS];  /* dyads in the lane / wave / group buckets */
+    uint64_t bucket_cost[TC_NUM_BUCKETS];   /* sum of |N(u)|+|N(v)| per bucket */
+} tc_graph_info;
+
+/* Degree-bucket thresholds and launch sizes.  A dyad with key
+ * k = |N(u)| + |N(v)| - 2 (the thesis's uniform-distribution workload estimate,
+ * figure "Canonical Dyad (uniform distr.)") runs one lane per dyad when k < t0,
+ * one wavefront per dyad when t0 <= k < t1, one workgroup per dyad when k >= t1. */
+typedef struct {
+    uint32_t t0, t1;
+    uint32_t lane_blocks;    /* grid cap, lane kernel (256-thread blocks) */
+    uint32_t wave_blocks;    /* resident one-wave blocks, wave kernel */
+    uint32_t group_blocks;   /* resident 256-thread blocks, group kernel */
+} tc_tuning;
+
+/* Accumulated device time of the census kernels, per bucket (lane, wave,
+ * group), measured with HIP events recorded on the context's stream. */
+typedef struct {
+    double ms[TC_NUM_BUCKETS];
+    uint64_t launches[TC_NUM_BUCKETS];
+    uint64_t census_calls;
+} tc_kernel_stats;
+
+/* Serving statistics (tc_submit / tc_poll). */
+typedef struct {
+    uint64_t submitted, completed, rounds;
+    uint64_t resident_graphs;
+    uint64_t bytes_in_flight;
+    double p50_ms, p99_ms;         /* submit -> completion latency */
+    double mean_admission_ms;      /* submit -> admission wait */
+} tc_serve_stats;
+
+/* Creates a context on HIP device `device`.  hbm_budget_bytes bounds the device
+ * memory of jobs admitted by tc_submit (0 = 90% of free memory).  hip_stream,
+ * when not null, is a hipStream_t the context uses instead of its own (the
+ * caller keeps it alive until tc_context_destroy).  *out receives the handle. */
+int tc_context_create(int device, uint64_t hbm_budget_bytes, void* hip_stream, tc_context* out);
+
+/* Stops the serving loop (pending tickets finish with TC_ERR_SHUTDOWN), frees
+ * every graph still owned by the context and the context itself. */
+int tc_context_destroy(tc_context ctx);
+
+/* Builds a resident device graph from m arcs src[i] -> dst[i] (0-based int32
+ * ids in [0, n)).  src/dst are read during the call only; host pointers unless
+ * TC_BUILD_DEVICE_PTRS.  Loops and repeated arcs are dropped (counted in info)
+ * unless TC_BUILD_STRICT, which rejects them.  Errors: TC_ERR_ARG (null pointer,
+ * n < 0, m < 0, id out of range, strict violation), TC_ERR_RANGE (n too large),
+ * TC_ERR_NOMEM, TC_ERR_DEVICE.  info may be null. */
+int tc_build_graph(tc_context ctx, int32_t n, int64_t m, const int32_t* src, const int32_t* dst,
+                   uint32_t flags, tc_graph* out, tc_graph_info* info);
+
+/* Copies the build information of g into *info. */
+int tc_graph_get_info(tc_context ctx, tc_graph g, tc_graph_info* info);
+
+/* Frees g.  TC_ERR_BUSY while tickets that use g are pending. */
+int tc_graph_release(tc_context ctx, tc_graph g);
+
+/* Synchronous census: counts[16] (host) receives the 16 class counts of g. */
+int tc_census(tc_context ctx, tc_graph g, uint64_t counts[16]);
+
+/* Partial census over the canonical dyads (u, v) with u in [u_begin, u_end):
+ * the local census of one task queue (figure "Subquadratic Triad Census
+ * Algorithm based on distributed task queues").  partial[0] (class 003) is 0;
+ * summing the partials of a partition of [0, n) gives counts[1..15]. */
+int tc_census_range(tc_context ctx, tc_graph g, int32_t u_begin, int32_t u_end, uint64_t partial[16]);
+
+/* Census of `count` resident graphs in one persistent launch, replayed from a
+ * captured HIP graph when the same set of graphs is passed again.
+ * counts (host) receives count*16 values, graph i at counts[16*i]. */
+int tc_census_batch(tc_context ctx, const tc_graph* graphs, int32_t count, uint64_t* counts);
+
+/* Same result as tc_census_batch, but one tc_census-style launch sequence per
+ * graph (the per-graph baseline of the batched mode). */
+int tc_census_each(tc_context ctx, const tc_graph* graphs, int32_t count, uint64_t* counts);
+
+/* Queues a census of g for the serving loop and returns at once.  The loop
+ * admits jobs while their device footprint fits the budget, runs all admitted
+ * jobs of a round in one batched launch on a free stream, and overlaps rounds.
+ * g must stay alive until the ticket is polled done (release returns BUSY). */
+int tc_submit(tc_context ctx, tc_graph g, tc_ticket* out);
+
+/* Non-blocking: *done = 1 and counts[16] filled when the ticket has finished
+ * (the ticket is then retired), *done = 0 otherwise.  TC_ERR_NOT_FOUND for an
+ * unknown or retired ticket, TC_ERR_SHUTDOWN if the context is shutting down. */
+int tc_poll(tc_context ctx, tc_ticket ticket, uint64_t counts[16], int* done);
+
+/* Serving statistics since the context was created (or last reset). */
+int tc_serve_get_stats(tc_context ctx, tc_serve_stats* out);
+int tc_serve_reset_stats(tc_context ctx);
+
+/* Tuning: thresholds apply to graphs built afterwards and to graphs passed to
+ * tc_graph_rebucket; launch sizes apply to the next census call. */
+int tc_set_tuning(tc_context ctx, const tc_tuning* t);
+int tc_get_tuning(tc_context ctx, tc_tuning* t);
+int tc_graph_rebucket(tc_context ctx, tc_graph g);
+
+/* Searches thresholds and launch sizes on the given sample graphs (timing
+ * tc_census_batch over them), applies the best to the context and writes it to
+ * *best (may be null).  cache_path, when not null, is a JSON file keyed by
+ * device name, CU count and the sample's degree signature: a hit skips the search. */
+int tc_autotune(tc_context ctx, const tc_graph* sample, int32_t count, const char* cache_path, tc_tuning* best);
+
+/* Kernel timing: when enabled, every census records HIP events around each
+ * bucket kernel on the context stream and accumulates their durations. */
+int tc_set_timing(tc_context ctx, int enable);
+int tc_get_kernel_stats(tc_context ctx, tc_kernel_stats* out);
+int tc_reset_kernel_stats(tc_context ctx);
+
+/* The library's 64 -> 16 class table (host only, needs no device). */
+int tc_class_table(uint8_t out[64]);
+
+/* Static string for a status code. */
+const char* tc_status_string(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TC_H */

@@ -1,0 +1,378 @@
+// C ABI of libtc: contexts, resident graphs, single-graph and range census.
+// Batched, served and autotuned modes live in tc_batch.hip / tc_serve.cpp.
+#include "tc_api_internal.h"
+
+#include <cstring>
+#include <new>
+
+using namespace tc;
+
+namespace tc {
+
+int status_from_hip(hipError_t e) {
+    if (e == hipSuccess) return TC_OK;
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) return TC_ERR_NOMEM;
+    return TC_ERR_DEVICE;
+}
+
+void finalize_counts(int64_t n, const unsigned long long* raw, uint64_t out[16]) {
+    typedef unsigned __int128 u128;
+    u128 total = n >= 3 ? (u128)n * (u128)(n - 1) * (u128)(n - 2) / 6 : 0;
+    u128 sum = 0;
+    for (int k = 1; k < kNumClasses; ++k) {
+        out[k] = raw[k];
+        sum += raw[k];
+    }
+    out[0] = (uint64_t)(total - sum);
+}
+
+census_slices full_slices(const device_graph& g) {
+    census_slices sl;
+    for (int b = 0; b < kBuckets; ++b) {
+        sl.begin[b] = g.bucket_off[b];
+        sl.end[b] = g.bucket_off[b + 1];
+    }
+    return sl;
+}
+
+census_config config_of(const tc_tuning& t) {
+    census_config c;
+    c.lane_blocks = t.lane_blocks;
+    c.wave_blocks = t.wave_blocks;
+    c.group_blocks = t.group_blocks;
+    return c;
+}
+
+void fill_info(const tc_graph_s* g, tc_graph_info* info) {
+    *info = g->info;
+    info->device_bytes = device_graph_bytes(g->g);
+    info->asym_dyads = (int64_t)(g->g.p - g->g.mutual);
+    info->mutual_dyads = (int64_t)g->g.mutual;
+    for (int b = 0; b < kBuckets; ++b) {
+        info->bucket_dyads[b] = g->g.bucket_off[b + 1] - g->g.bucket_off[b];
+        info->bucket_cost[b] = g->g.bucket_cost[b];
+    }
+}
+
+// Runs the three bucket kernels over `sl` and copies the 16 raw sums to host.
+int run_census_locked(tc_context_s* ctx, const device_graph& g, const census_slices& sl,
+                      unsigned long long raw[16]) {
+    hipEvent_t* ev = ctx->timing ? ctx->ev : nullptr;
+    hipError_t e = census_launch(g, sl, ctx->acc, ctx->counters, config_of(ctx->tuning), ctx->stream, ev);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(ctx->host_raw, ctx->acc, sizeof(unsigned long long) * kNumClasses,
+                           hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return status_from_hip(e);
+    std::memcpy(raw, ctx->host_raw, sizeof(unsigned long long) * kNumClasses);
+    if (ev) {
+        for (int b = 0; b < kBuckets; ++b) {
+            if (sl.end[b] <= sl.begin[b]) continue;
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, ev[2 * b], ev[2 * b + 1]) == hipSuccess) {
+                ctx->kstats.ms[b] += ms;
+                ctx->kstats.launches[b] += 1;
+            }
+        }
+    }
+    ctx->kstats.census_calls += 1;
+    return TC_OK;
+}
+
+namespace {
+
+__global__ void k_bounds(const dyad_rec* dyads, const uint64_t* off, uint32_t u0, uint32_t u1, uint64_t* out) {
+    int b = threadIdx.x >> 1;
+    if (b >= kBuckets) return;
+    uint32_t key = (threadIdx.x & 1) ? u1 : u0;
+    uint64_t lo = off[b], hi = off[b + 1];
+    while (lo < hi) {
+        uint64_t mid = lo + ((hi - lo) >> 1);
+        if (dyads[mid].u < key) lo = mid + 1; else hi = mid;
+    }
+    out[threadIdx.x] = lo;
+}
+
+}  // namespace
+
+}  // namespace tc
+
+// ---------------------------------------------------------------------------
+
+extern "C" {
+
+const char* tc_status_string(int s) {
+    switch (s) {
+        case TC_OK: return "ok";
+        case TC_ERR_ARG: return "invalid argument";
+        case TC_ERR_RANGE: return "size out of range";
+        case TC_ERR_NOMEM: return "out of memory";
+        case TC_ERR_DEVICE: return "device error";
+        case TC_ERR_BUSY: return "graph busy";
+        case TC_ERR_NOT_FOUND: return "ticket not found";
+        case TC_ERR_SHUTDOWN: return "context shutting down";
+        default: return "unknown status";
+    }
+}
+
+int tc_class_table(uint8_t out[64]) {
+    if (!out) return TC_ERR_ARG;
+    std::memcpy(out, kTable.t, 64);
+    return TC_OK;
+}
+
+int tc_context_create(int device, uint64_t hbm_budget_bytes, void* hip_stream, tc_context* out) {
+    if (!out) return TC_ERR_ARG;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return TC_ERR_ARG;
+    if (hipSetDevice(device) != hipSuccess) return TC_ERR_DEVICE;
+    tc_context_s* ctx = new (std::nothrow) tc_context_s();
+    if (!ctx) return TC_ERR_NOMEM;
+    ctx->device = device;
+    hipError_t e = hipSuccess;
+    if (hip_stream) {
+        ctx->stream = (hipStream_t)hip_stream;
+        ctx->own_stream = false;
+    } else {
+        e = hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking);
+        ctx->own_stream = true;
+    }
+    if (e == hipSuccess) e = census_upload_table();
+    if (e == hipSuccess) e = hipMalloc((void**)&ctx->acc, sizeof(unsigned long long) * kNumClasses);
+    if (e == hipSuccess) e = hipMalloc((void**)&ctx->counters, sizeof(unsigned int) * 64);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&ctx->host_raw, sizeof(unsigned long long) * kNumClasses);
+    for (int i = 0; i < 2 * kBuckets && e == hipSuccess; ++i) e = hipEventCreate(&ctx->ev[i]);
+    if (e == hipSuccess) {
+        size_t free_b = 0, total_b = 0;
+        e = hipMemGetInfo(&free_b, &total_b);
+        ctx->budget = hbm_budget_bytes ? hbm_budget_bytes : (uint64_t)(0.9 * (double)free_b);
+        hipDeviceProp_t prop;
+        if (e == hipSuccess) e = hipGetDeviceProperties(&prop, device);
+        if (e == hipSuccess) {
+            ctx->cu_count = prop.multiProcessorCount;
+            std::strncpy(ctx->arch, prop.gcnArchName, sizeof(ctx->arch) - 1);
+        }
+    }
+    if (e != hipSuccess) {
+        tc_context_destroy(ctx);
+        return status_from_hip(e);
+    }
+    ctx->tuning = default_tuning(ctx->cu_count);
+    *out = ctx;
+    return TC_OK;
+}
+
+int tc_context_destroy(tc_context ctx) {
+    if (!ctx) return TC_ERR_ARG;
+    (void)hipSetDevice(ctx->device);
+    serve_shutdown(ctx);
+    batch_release_all(ctx);
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        for (tc_graph g : ctx->graphs) {
+            free_device_graph(&g->g);
+            delete g;
+        }
+        ctx->graphs.clear();
+    }
+    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    for (int i = 0; i < 2 * kBuckets; ++i)
+        if (ctx->ev[i]) (void)hipEventDestroy(ctx->ev[i]);
+    if (ctx->acc) (void)hipFree(ctx->acc);
+    if (ctx->counters) (void)hipFree(ctx->counters);
+    if (ctx->host_raw) (void)hipHostFree(ctx->host_raw);
+    if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+    return TC_OK;
+}
+
+int tc_build_graph(tc_context ctx, int32_t n, int64_t m, const int32_t* src, const int32_t* dst, uint32_t flags,
+                   tc_graph* out, tc_graph_info* info) {
+    if (!ctx || !out || n < 0 || m < 0) return TC_ERR_ARG;
+    if (m > 0 && (!src || !dst)) return TC_ERR_ARG;
+    if (flags & ~(uint32_t)(TC_BUILD_STRICT | TC_BUILD_DEVICE_PTRS)) return TC_ERR_ARG;
+    if (n > kMaxN) return TC_ERR_RANGE;
+    if (hipSetDevice(ctx->device) != hipSuccess) return TC_ERR_DEVICE;
+    tc_graph_s* g = new (std::nothrow) tc_graph_s();
+    if (!g) return TC_ERR_NOMEM;
+
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    const int32_t *s_dev = src, *d_dev = dst;
+    int32_t* tmp = nullptr;
+    hipError_t e = hipSuccess;
+    if (!(flags & TC_BUILD_DEVICE_PTRS) && m > 0) {
+        e = hipMalloc((void**)&tmp, sizeof(int32_t) * 2 * (size_t)m);
+        if (e == hipSuccess) e = hipMemcpyAsync(tmp, src, sizeof(int32_t) * m, hipMemcpyHostToDevice, ctx->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(tmp + m, dst, sizeof(int32_t) * m, hipMemcpyHostToDevice, ctx->stream);
+        s_dev = tmp;
+        d_dev = tmp + m;
+    }
+    build_status st;
+    if (e == hipSuccess)
+        st = build_graph_device(n, m, s_dev, d_dev, ctx->tuning.t0, ctx->tuning.t1, ctx->stream, &g->g);
+    if (tmp) {
+        (void)hipStreamSynchronize(ctx->stream);
+        (void)hipFree(tmp);
+    }
+    int rc = TC_OK;
+    if (e != hipSuccess) rc = status_from_hip(e);
+    else if (st.bad_ids) rc = TC_ERR_ARG;
+    else if (st.too_large) rc = TC_ERR_RANGE;
+    else if (!st.ok) rc = status_from_hip(st.hip);
+    else if ((flags & TC_BUILD_STRICT) && (st.self_loops > 0 || st.duplicates > 0)) rc = TC_ERR_ARG;
+    if (rc != TC_OK) {
+        free_device_graph(&g->g);
+        delete g;
+        return rc;
+    }
+    g->info = tc_graph_info{};
+    g->info.arcs_in = m;
+    g->info.arcs_kept = st.arcs_kept;
+    g->info.self_loops_dropped = st.self_loops;
+    g->info.duplicates_dropped = m - st.self_loops - st.arcs_kept;
+    g->info.max_degree = st.max_degree;
+    g->info.sum_d2 = st.sum_d2;
+    ctx->graphs.insert(g);
+    *out = g;
+    if (info) fill_info(g, info);
+    return TC_OK;
+}
+
+int tc_graph_get_info(tc_context ctx, tc_graph g, tc_graph_info* info) {
+    if (!ctx || !g || !info) return TC_ERR_ARG;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    if (!ctx->graphs.count(g)) return TC_ERR_ARG;
+    fill_info(g, info);
+    return TC_OK;
+}
+
+int tc_graph_release(tc_context ctx, tc_graph g) {
+    if (!ctx || !g) return TC_ERR_ARG;
+    if (hipSetDevice(ctx->device) != hipSuccess) return TC_ERR_DEVICE;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    if (!ctx->graphs.count(g)) return TC_ERR_ARG;
+    if (g->pending.load() > 0) return TC_ERR_BUSY;
+    batch_forget_graph_locked(ctx, g);
+    (void)hipStreamSynchronize(ctx->stream);
+    ctx->graphs.erase(g);
+    free_device_graph(&g->g);
+    delete g;
+    return TC_OK;
+}
+
+int tc_census(tc_context ctx, tc_graph g, uint64_t counts[16]) {
+    if (!ctx || !g || !counts) return TC_ERR_ARG;
+    if (hipSetDevice(ctx->device) != hipSuccess) return TC_ERR_DEVICE;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    if (!ctx->graphs.count(g)) return TC_ERR_ARG;
+    unsigned long long raw[16];
+    int rc = run_census_locked(ctx, g->g, full_slices(g->g), raw);
+    if (rc != TC_OK) return rc;
+    finalize_counts(g->g.n, raw, counts);
+    return TC_OK;
+}
+
+int tc_census_range(tc_context ctx, tc_graph g, int32_t u_begin, int32_t u_end, uint64_t partial[16]) {
+    if (!ctx || !g || !partial) return TC_ERR_ARG;
+    if (hipSetDevice(ctx->device) != hipSuccess) return TC_ERR_DEVICE;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    if (!ctx->graphs.count(g)) return TC_ERR_ARG;
+    int32_t n = g->g.n;
+    if (u_begin < 0) u_begin = 0;
+    if (u_end > n) u_end = n;
+    unsigned long long raw[16] = {0};
+    if (u_begin < u_end && g->g.p > 0) {
+        uint64_t *off_dev = nullptr, *bnd_dev = nullptr;
+        uint64_t bnd[2 * kBuckets];
+        hipError_t e = hipMalloc((void**)&off_dev, sizeof(uint64_t) * (kBuckets + 1 + 2 * kBuckets));
+        if (e != hipSuccess) return status_from_hip(e);
+        bnd_dev = off_dev + kBuckets + 1;
+        e = hipMemcpyAsync(off_dev, g->g.bucket_off, sizeof(uint64_t) * (kBuckets + 1), hipMemcpyHostToDevice,
+                           ctx->stream);
+        if (e == hipSuccess) {
+            hipLaunchKernelGGL(k_bounds, dim3(1), dim3(64), 0, ctx->stream, g->g.dyads, off_dev, (uint32_t)u_begin,
+                               (uint32_t)u_end, bnd_dev);
+            e = hipGetLastError();
+        }
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(bnd, bnd_dev, sizeof(bnd), hipMemcpyDeviceToHost, ctx->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+        (void)hipFree(off_dev);
+        if (e != hipSuccess) return status_from_hip(e);
+        census_slices sl;
+        for (int b = 0; b < kBuckets; ++b) {
+            sl.begin[b] = bnd[2 * b];
+            sl.end[b] = bnd[2 * b + 1];
+        }
+        int rc = run_census_locked(ctx, g->g, sl, raw);
+        if (rc != TC_OK) return rc;
+    }
+    partial[0] = 0;
+    for (int k = 1; k < kNumClasses; ++k) partial[k] = raw[k];
+    return TC_OK;
+}
+
+int tc_census_each(tc_context ctx, const tc_graph* graphs, int32_t count, uint64_t* counts) {
+    if (!ctx || count < 0 || (count > 0 && (!graphs || !counts))) return TC_ERR_ARG;
+    if (hipSetDevice(ctx->device) != hipSuccess) return TC_ERR_DEVICE;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    for (int32_t i = 0; i < count; ++i)
+        if (!graphs[i] || !ctx->graphs.count(graphs[i])) return TC_ERR_ARG;
+    for (int32_t i = 0; i < count; ++i) {
+        unsigned long long raw[16];
+        int rc = run_census_locked(ctx, graphs[i]->g, full_slices(graphs[i]->g), raw);
+        if (rc != TC_OK) return rc;
+        finalize_counts(graphs[i]->g.n, raw, counts + 16 * (size_t)i);
+    }
+    return TC_OK;
+}
+
+int tc_set_tuning(tc_context ctx, const tc_tuning* t) {
+    if (!ctx || !t) return TC_ERR_ARG;
+    if (t->t0 > t->t1 || t->lane_blocks == 0 || t->wave_blocks == 0 || t->group_blocks == 0) return TC_ERR_ARG;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->tuning = *t;
+    return TC_OK;
+}
+
+int tc_get_tuning(tc_context ctx, tc_tuning* t) {
+    if (!ctx || !t) return TC_ERR_ARG;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    *t = ctx->tuning;
+    return TC_OK;
+}
+
+int tc_graph_rebucket(tc_context ctx, tc_graph g) {
+    if (!ctx || !g) return TC_ERR_ARG;
+    if (hipSetDevice(ctx->device) != hipSuccess) return TC_ERR_DEVICE;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    if (!ctx->graphs.count(g)) return TC_ERR_ARG;
+    if (g->pending.load() > 0) return TC_ERR_BUSY;
+    if (g->g.t0 == ctx->tuning.t0 && g->g.t1 == ctx->tuning.t1) return TC_OK;
+    batch_forget_graph_locked(ctx, g);
+    return status_from_hip(bucket_dyads(&g->g, ctx->tuning.t0, ctx->tuning.t1, ctx->stream));
+}
+
+int tc_set_timing(tc_context ctx, int enable) {
+    if (!ctx) return TC_ERR_ARG;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->timing = enable != 0;
+    return TC_OK;
+}
+
+int tc_get_kernel_stats(tc_context ctx, tc_kernel_stats* out) {
+    if (!ctx || !out) return TC_ERR_ARG;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    *out = ctx->kstats;
+    return TC_OK;
+}
+
+int tc_reset_kernel_stats(tc_context ctx) {
+    if (!ctx) return TC_ERR_ARG;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->kstats = tc_kernel_stats{};
+    return TC_OK;
+}
+
+}  // extern "C"

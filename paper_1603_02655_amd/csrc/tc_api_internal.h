@@ -1,0 +1,74 @@
+// Host-side state behind the C ABI handles.
+#pragma once
+#include <atomic>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <set>
+#include <thread>
+#include <vector>
+
+#include "../../include/tc.h"
+#include "tc_census.h"
+
+struct tc_graph_s {
+    tc::device_graph g;
+    tc_graph_info info{};
+    std::atomic<int> pending{0};     // tickets in flight that use this graph
+};
+
+namespace tc {
+struct batch_plan;     // tc_batch.hip
+struct serve_state;    // tc_serve.cpp
+}
+
+struct tc_context_s {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    uint64_t budget = 0;
+    int cu_count = 0;
+    char arch[64] = {0};
+    std::mutex mu;                      // serialises work on `stream` and the buffers below
+    unsigned long long* acc = nullptr;  // 16 accumulators (device)
+    unsigned int* counters = nullptr;   // work counters (device)
+    unsigned long long* host_raw = nullptr;  // pinned copy of acc
+    hipEvent_t ev[2 * tc::kBuckets] = {};
+    bool timing = false;
+    tc_kernel_stats kstats{};
+    tc_tuning tuning{};
+    std::set<tc_graph> graphs;
+    tc::batch_plan* batch = nullptr;    // cached batched launch (captured hipGraph), owned
+    tc::serve_state* serve = nullptr;   // serving loop, started on first submit, owned
+};
+
+namespace tc {
+
+int status_from_hip(hipError_t e);
+void finalize_counts(int64_t n, const unsigned long long* raw, uint64_t out[16]);
+census_slices full_slices(const device_graph& g);
+census_config config_of(const tc_tuning& t);
+void fill_info(const tc_graph_s* g, tc_graph_info* info);
+int run_census_locked(tc_context_s* ctx, const device_graph& g, const census_slices& sl, unsigned long long raw[16]);
+
+inline tc_tuning default_tuning(int cu_count) {
+    tc_tuning t;
+    int cu = cu_count > 0 ? cu_count : 256;
+    t.t0 = 64;      // lane mode for k < 64
+    t.t1 = 4096;    // wave mode for 64 <= k < 4096, group mode above
+    t.lane_blocks = (uint32_t)cu * 8;
+    t.wave_blocks = (uint32_t)cu * 10;
+    t.group_blocks = (uint32_t)cu * 2;
+    return t;
+}
+
+// batched mode (tc_batch.hip)
+void batch_release_all(tc_context_s* ctx);
+void batch_forget_graph_locked(tc_context_s* ctx, tc_graph g);
+
+// serving loop (tc_serve.cpp)
+void serve_shutdown(tc_context_s* ctx);
+
+}  // namespace tc

@@ -7,6 +7,8 @@ the 003 finalisation).  Prints one JSON line.
 
   python bench.py [--steps K] [--warmup W] [--workload rmat|citation|er]
                   [--cpu-seconds S] [--no-cpu-baseline]
+  python bench.py --workload batch [--batch-count 4096]   # batched mode vs per-graph launches
+  python bench.py --workload serve [--rate 2000] [--duration 10] [--pool 64]
 """
 from __future__ import annotations
 
@@ -38,6 +40,191 @@ def workload(name: str):
     if name == "er":
         return synth.config_er_small()
     raise SystemExit(f"unknown workload {name}")
+
+
+def _gen_batch(i):
+    from paper_1603_02655_amd import synth
+    return synth.batch_graph(i)
+
+
+def _gen_serve(i):
+    from paper_1603_02655_amd import synth
+    return synth.serving_graph(i)
+
+
+def generate_pool(fn, count):
+    """Graphs 0..count-1 of a pool, drawn in worker processes (no GPU there)."""
+    from concurrent.futures import ProcessPoolExecutor
+    workers = max(1, min(16, os.cpu_count() or 1))
+    with ProcessPoolExecutor(max_workers=workers) as ex:
+        return list(ex.map(fn, range(count), chunksize=max(1, count // (4 * workers))))
+
+
+def bench_batch(args):
+    """Batched census of a pool of uneven R-MAT graphs: one persistent launch
+    (captured HIP graph, autotuned thresholds) against one launch sequence per
+    graph, on the same resident graphs."""
+    from paper_1603_02655_amd import tc
+    log(f"[bench] generating {args.batch_count} batch graphs")
+    pool = generate_pool(_gen_batch, args.batch_count)
+    ctx = tc.Context(0)
+    log("[bench] building")
+    hs = [ctx.build_graph(g.n, g.src, g.dst) for g in pool]
+    arcs = sum(int(h.info["arcs_kept"]) for h in hs)
+    rng = np.random.default_rng(1)
+    sample = [hs[i] for i in rng.choice(len(hs), size=min(64, len(hs)), replace=False)]
+    t = time.perf_counter()
+    tuning = ctx.autotune(sample)
+    tune_s = time.perf_counter() - t
+    for h in hs:
+        ctx.rebucket(h)
+    log(f"[bench] autotuned in {tune_s:.1f}s: {tuning}")
+    each = ctx.census_each(hs)
+    tc.device_synchronize(0)
+    t = time.perf_counter()
+    each = ctx.census_each(hs)
+    tc.device_synchronize(0)
+    each_s = time.perf_counter() - t
+    for _ in range(args.warmup):
+        out = ctx.census_batch(hs)
+    assert out.tolist() == each.tolist(), "batched and per-graph counts differ"
+    ctx.reset_kernel_stats()
+    ctx.set_timing(True)
+    tc.device_synchronize(0)
+    t = time.perf_counter()
+    for _ in range(args.steps):
+        out = ctx.census_batch(hs)
+    tc.device_synchronize(0)
+    el = time.perf_counter() - t
+    ks = ctx.kernel_stats()
+    ctx.set_timing(False)
+    assert out.tolist() == each.tolist()
+    step_s = el / args.steps
+    sum_cost = sum(sum(h.info["bucket_cost"]) for h in hs)
+    dyads = sum(sum(h.info["bucket_dyads"]) for h in hs)
+    launch_ms = ks["batch_ms"] / max(1, ks["batch_launches"])
+    bytes_alg = 4.0 * sum_cost + 8.0 * dyads
+    achieved = bytes_alg / (launch_ms / 1000.0) / 1e9 if launch_ms > 0 else 0.0
+    line = {
+        "metric": "census arcs/sec (batched)", "value": arcs / step_s, "unit": "arcs/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1000 * step_s, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u32/u64", "data": "synthetic",
+        "config": {"workload": f"batch of {len(hs)} R-MAT digraphs, n log-uniform [50, 20000], "
+                               "mean out-degree U[3,30], reciprocity 0.10", "graphs": len(hs), "arcs": arcs,
+                   "tuning": tuning},
+        "graphs_per_s": len(hs) / step_s,
+        "per_graph_launches": {"graphs_per_s": len(hs) / each_s, "arcs_per_s": arcs / each_s,
+                               "ms": 1000 * each_s},
+        "speedup_vs_per_graph": each_s / step_s,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_census_batch",
+                     "kernel_ms": launch_ms},
+        "autotune_s": tune_s,
+    }
+    for h in hs:
+        h.release()
+    ctx.close()
+    print(json.dumps(line), flush=True)
+
+
+def bench_serve(args):
+    """Served census: Poisson arrivals of requests for graphs of a resident
+    pool; results checked against the same graphs' census run alone."""
+    from paper_1603_02655_amd import tc
+    log(f"[bench] generating serving pool of {args.pool}")
+    pool = generate_pool(_gen_serve, args.pool)
+    ctx = tc.Context(0)
+    hs = [ctx.build_graph(g.n, g.src, g.dst) for g in pool]
+    arcs = np.array([int(h.info["arcs_kept"]) for h in hs])
+    alone = ctx.census_each(hs)
+    # per-graph launch baseline over a random request sequence
+    rng = np.random.default_rng(5)
+    seq = rng.integers(0, len(hs), 200)
+    t = time.perf_counter()
+    for i in seq:
+        ctx.census(hs[i])
+    base_s = time.perf_counter() - t
+    base_rps = len(seq) / base_s
+    from paper_1603_02655_amd import synth
+    runs = []
+    all_ok = True
+    for rate in [float(x) for x in str(args.rate).split(",")]:
+        arrivals = synth.poisson_arrivals(rate, args.duration + 1.0, synth.rng_for(5, int(rate)))
+        picks = rng.integers(0, len(hs), arrivals.size)
+        log(f"[bench] serving {arrivals.size} requests at {rate:.0f}/s for {args.duration + 1:.0f}s")
+        ctx.serve_reset_stats()
+        sub_q = []
+        lock = threading.Lock()
+        t0 = time.perf_counter()
+
+        def submitter():
+            for k in range(arrivals.size):
+                delay = arrivals[k] - (time.perf_counter() - t0)
+                if delay > 0:
+                    time.sleep(delay)
+                tk = ctx.submit(hs[picks[k]])
+                with lock:
+                    sub_q.append((tk, k, time.perf_counter()))
+
+        th = threading.Thread(target=submitter)
+        th.start()
+        outstanding = []
+        results = {}
+        lat = {}
+        while True:
+            with lock:
+                outstanding.extend(sub_q)
+                sub_q.clear()
+            keep = []
+            for n_polled, (tk, k, ts) in enumerate(outstanding):
+                if n_polled >= 512:
+                    keep.append((tk, k, ts))
+                    continue
+                r = ctx.poll(tk)
+                if r is None:
+                    keep.append((tk, k, ts))
+                else:
+                    results[k] = r
+                    lat[k] = (time.perf_counter() - ts) * 1000.0
+            outstanding = keep
+            if not th.is_alive() and not outstanding and not sub_q:
+                break
+            time.sleep(0.0002)
+        th.join()
+        total_s = time.perf_counter() - t0
+        st = ctx.serve_stats()
+        ok = all(results[i].tolist() == alone[picks[i]].tolist() for i in range(arrivals.size))
+        all_ok &= ok
+        meas = [i for i in range(arrivals.size) if arrivals[i] >= 1.0]
+        ml = np.array([lat[i] for i in meas]) if meas else np.zeros(1)
+        runs.append({"rate": rate, "requests": int(arrivals.size), "measured": len(meas),
+                     "wall_s": total_s, "completed_per_s": arrivals.size / total_s,
+                     "offered_arcs_per_s": float(arcs[picks].mean() * rate),
+                     "achieved_arcs_per_s": float(arcs[picks].sum() / total_s),
+                     "p50_ms": float(np.percentile(ml, 50)), "p99_ms": float(np.percentile(ml, 99)),
+                     "rounds": st["rounds"], "mean_admission_ms": st["mean_admission_ms"],
+                     "results_equal_alone": ok})
+        log(f"[bench] rate {rate}: {runs[-1]}")
+    head = runs[-1]
+    line = {
+        "metric": "served census throughput + p50/p99 latency", "value": head["completed_per_s"],
+        "unit": "requests/s", "n_gpus": 1, "steps": head["requests"], "warmup": 0,
+        "ms_per_step": head["p50_ms"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u32/u64", "data": "synthetic",
+        "config": {"workload": f"serving pool of {len(hs)} graphs (even ER, odd R-MAT r=0.10), n log-uniform "
+                               "[1e3, 1e6], mean out-degree U[4,32]; Poisson arrivals",
+                   "duration_s": args.duration, "pool_arcs": int(arcs.sum())},
+        "runs": runs,
+        "per_graph_launches_rps": base_rps,
+        "results_equal_alone": all_ok,
+    }
+    ok = all_ok
+    for h in hs:
+        h.release()
+    ctx.close()
+    print(json.dumps(line), flush=True)
+    if not ok:
+        sys.exit(1)
 
 
 def dyad_work(g0):
@@ -106,11 +293,20 @@ def main():
     ap.add_argument("--workload", default="rmat")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batch-count", type=int, default=4096)
+    ap.add_argument("--rate", default="2000", help="comma-separated arrival rates (requests/s)")
+    ap.add_argument("--duration", type=float, default=5.0)
+    ap.add_argument("--pool", type=int, default=64)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the census of one graph is "
               "a single-device job here.", file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "batch":
+        return bench_batch(args)
+    if args.workload == "serve":
+        return bench_serve(args)
 
     from paper_1603_02655_amd import tc
 

@@ -75,6 +75,7 @@ typedef struct {
     uint32_t lane_blocks;    /* grid cap, lane kernel (256-thread blocks) */
     uint32_t wave_blocks;    /* resident one-wave blocks, wave kernel */
     uint32_t group_blocks;   /* resident 256-thread blocks, group kernel */
+    uint32_t batch_blocks;   /* resident 256-thread blocks, batched (persistent) kernel */
 } tc_tuning;
 
 /* Accumulated device time of the census kernels, per bucket (lane, wave,
@@ -83,6 +84,8 @@ typedef struct {
     double ms[TC_NUM_BUCKETS];
     uint64_t launches[TC_NUM_BUCKETS];
     uint64_t census_calls;
+    double batch_ms;             /* replays of the captured batched launch */
+    uint64_t batch_launches;
 } tc_kernel_stats;
 
 /* Serving statistics (tc_submit / tc_poll). */
@@ -143,10 +146,26 @@ int tc_census_each(tc_context ctx, const tc_graph* graphs, int32_t count, uint64
  * g must stay alive until the ticket is polled done (release returns BUSY). */
 int tc_submit(tc_context ctx, tc_graph g, tc_ticket* out);
 
-/* Non-blocking: *done = 1 and counts[16] filled when the ticket has finished
- * (the ticket is then retired), *done = 0 otherwise.  TC_ERR_NOT_FOUND for an
- * unknown or retired ticket, TC_ERR_SHUTDOWN if the context is shutting down. */
+/* A request that carries its graph: n and m host arcs src[i] -> dst[i], copied
+ * during the call.  The serving loop admits it when the build footprint fits
+ * the budget, builds the graph on a serving stream, censuses it in a round and
+ * frees it.  flags may hold TC_BUILD_STRICT.  Argument errors are returned at
+ * once; build errors (bad ids, strict violations) by tc_poll. */
+int tc_submit_arcs(tc_context ctx, int32_t n, int64_t m, const int32_t* src, const int32_t* dst, uint32_t flags,
+                   tc_ticket* out);
+
+/* Non-blocking.  When the ticket has finished, *done = 1 and the ticket is
+ * retired: the return value is its status (counts[16] filled when TC_OK;
+ * TC_ERR_NOMEM if its footprint exceeds the whole budget, TC_ERR_SHUTDOWN if
+ * the loop stopped before running it).  Otherwise *done = 0 and TC_OK is
+ * returned (TC_ERR_SHUTDOWN once the loop is stopping).  TC_ERR_NOT_FOUND for
+ * an unknown or already retired ticket. */
 int tc_poll(tc_context ctx, tc_ticket ticket, uint64_t counts[16], int* done);
+
+/* Stops the serving loop: running rounds finish, queued tickets end with
+ * TC_ERR_SHUTDOWN, later submissions fail with TC_ERR_SHUTDOWN.  The context
+ * stays usable for synchronous calls. */
+int tc_serve_stop(tc_context ctx);
 
 /* Serving statistics since the context was created (or last reset). */
 int tc_serve_get_stats(tc_context ctx, tc_serve_stats* out);
@@ -158,10 +177,13 @@ int tc_set_tuning(tc_context ctx, const tc_tuning* t);
 int tc_get_tuning(tc_context ctx, tc_tuning* t);
 int tc_graph_rebucket(tc_context ctx, tc_graph g);
 
-/* Searches thresholds and launch sizes on the given sample graphs (timing
- * tc_census_batch over them), applies the best to the context and writes it to
- * *best (may be null).  cache_path, when not null, is a JSON file keyed by
- * device name, CU count and the sample's degree signature: a hit skips the search. */
+/* Searches thresholds and launch sizes on the given sample graphs by
+ * coordinate descent (objective: wall time of tc_census for one sample graph,
+ * of tc_census_batch for several), applies the best to the context, rebuckets
+ * the sample graphs and writes it to *best (may be null).  cache_path, when not
+ * null, is a JSON file keyed by device name, CU count and the sample's degree
+ * signature: a hit skips the search; a search adds its result.  Counts never
+ * depend on the tuning. */
 int tc_autotune(tc_context ctx, const tc_graph* sample, int32_t count, const char* cache_path, tc_tuning* best);
 
 /* Kernel timing: when enabled, every census records HIP events around each

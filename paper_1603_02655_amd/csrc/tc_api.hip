@@ -79,6 +79,46 @@ int run_census_locked(tc_context_s* ctx, const device_graph& g, const census_sli
     return TC_OK;
 }
 
+int build_into(int32_t n, int64_t m, const int32_t* src, const int32_t* dst, uint32_t flags, uint32_t t0, uint32_t t1,
+               hipStream_t stream, device_graph* out, tc_graph_info* info) {
+    const int32_t *s_dev = src, *d_dev = dst;
+    int32_t* tmp = nullptr;
+    hipError_t e = hipSuccess;
+    if (!(flags & TC_BUILD_DEVICE_PTRS) && m > 0) {
+        e = hipMalloc((void**)&tmp, sizeof(int32_t) * 2 * (size_t)m);
+        if (e == hipSuccess) e = hipMemcpyAsync(tmp, src, sizeof(int32_t) * m, hipMemcpyHostToDevice, stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(tmp + m, dst, sizeof(int32_t) * m, hipMemcpyHostToDevice, stream);
+        s_dev = tmp;
+        d_dev = tmp + m;
+    }
+    build_status st;
+    if (e == hipSuccess) st = build_graph_device(n, m, s_dev, d_dev, t0, t1, stream, out);
+    if (tmp) {
+        (void)hipStreamSynchronize(stream);
+        (void)hipFree(tmp);
+    }
+    int rc = TC_OK;
+    if (e != hipSuccess) rc = status_from_hip(e);
+    else if (st.bad_ids) rc = TC_ERR_ARG;
+    else if (st.too_large) rc = TC_ERR_RANGE;
+    else if (!st.ok) rc = status_from_hip(st.hip);
+    else if ((flags & TC_BUILD_STRICT) && (st.self_loops > 0 || st.duplicates > 0)) rc = TC_ERR_ARG;
+    if (rc != TC_OK) {
+        free_device_graph(out);
+        return rc;
+    }
+    if (info) {
+        *info = tc_graph_info{};
+        info->arcs_in = m;
+        info->arcs_kept = st.arcs_kept;
+        info->self_loops_dropped = st.self_loops;
+        info->duplicates_dropped = m - st.self_loops - st.arcs_kept;
+        info->max_degree = st.max_degree;
+        info->sum_d2 = st.sum_d2;
+    }
+    return TC_OK;
+}
+
 namespace {
 
 __global__ void k_bounds(const dyad_rec* dyads, const uint64_t* off, uint32_t u0, uint32_t u1, uint64_t* out) {
@@ -195,44 +235,12 @@ int tc_build_graph(tc_context ctx, int32_t n, int64_t m, const int32_t* src, con
     if (hipSetDevice(ctx->device) != hipSuccess) return TC_ERR_DEVICE;
     tc_graph_s* g = new (std::nothrow) tc_graph_s();
     if (!g) return TC_ERR_NOMEM;
-
     std::lock_guard<std::mutex> lk(ctx->mu);
-    const int32_t *s_dev = src, *d_dev = dst;
-    int32_t* tmp = nullptr;
-    hipError_t e = hipSuccess;
-    if (!(flags & TC_BUILD_DEVICE_PTRS) && m > 0) {
-        e = hipMalloc((void**)&tmp, sizeof(int32_t) * 2 * (size_t)m);
-        if (e == hipSuccess) e = hipMemcpyAsync(tmp, src, sizeof(int32_t) * m, hipMemcpyHostToDevice, ctx->stream);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(tmp + m, dst, sizeof(int32_t) * m, hipMemcpyHostToDevice, ctx->stream);
-        s_dev = tmp;
-        d_dev = tmp + m;
-    }
-    build_status st;
-    if (e == hipSuccess)
-        st = build_graph_device(n, m, s_dev, d_dev, ctx->tuning.t0, ctx->tuning.t1, ctx->stream, &g->g);
-    if (tmp) {
-        (void)hipStreamSynchronize(ctx->stream);
-        (void)hipFree(tmp);
-    }
-    int rc = TC_OK;
-    if (e != hipSuccess) rc = status_from_hip(e);
-    else if (st.bad_ids) rc = TC_ERR_ARG;
-    else if (st.too_large) rc = TC_ERR_RANGE;
-    else if (!st.ok) rc = status_from_hip(st.hip);
-    else if ((flags & TC_BUILD_STRICT) && (st.self_loops > 0 || st.duplicates > 0)) rc = TC_ERR_ARG;
+    int rc = build_into(n, m, src, dst, flags, ctx->tuning.t0, ctx->tuning.t1, ctx->stream, &g->g, &g->info);
     if (rc != TC_OK) {
-        free_device_graph(&g->g);
         delete g;
         return rc;
     }
-    g->info = tc_graph_info{};
-    g->info.arcs_in = m;
-    g->info.arcs_kept = st.arcs_kept;
-    g->info.self_loops_dropped = st.self_loops;
-    g->info.duplicates_dropped = m - st.self_loops - st.arcs_kept;
-    g->info.max_degree = st.max_degree;
-    g->info.sum_d2 = st.sum_d2;
     ctx->graphs.insert(g);
     *out = g;
     if (info) fill_info(g, info);
@@ -330,7 +338,8 @@ int tc_census_each(tc_context ctx, const tc_graph* graphs, int32_t count, uint64
 
 int tc_set_tuning(tc_context ctx, const tc_tuning* t) {
     if (!ctx || !t) return TC_ERR_ARG;
-    if (t->t0 > t->t1 || t->lane_blocks == 0 || t->wave_blocks == 0 || t->group_blocks == 0) return TC_ERR_ARG;
+    if (t->t0 > t->t1 || t->lane_blocks == 0 || t->wave_blocks == 0 || t->group_blocks == 0 || t->batch_blocks == 0)
+        return TC_ERR_ARG;
     std::lock_guard<std::mutex> lk(ctx->mu);
     ctx->tuning = *t;
     return TC_OK;

@@ -52,6 +52,10 @@ census_slices full_slices(const device_graph& g);
 census_config config_of(const tc_tuning& t);
 void fill_info(const tc_graph_s* g, tc_graph_info* info);
 int run_census_locked(tc_context_s* ctx, const device_graph& g, const census_slices& sl, unsigned long long raw[16]);
+// Builds a device graph from host (or, with TC_BUILD_DEVICE_PTRS, device) arcs
+// on `stream`; returns a TC_* status and fills the build part of *info.
+int build_into(int32_t n, int64_t m, const int32_t* src, const int32_t* dst, uint32_t flags, uint32_t t0, uint32_t t1,
+               hipStream_t stream, device_graph* out, tc_graph_info* info);
 
 inline tc_tuning default_tuning(int cu_count) {
     tc_tuning t;
@@ -61,14 +65,17 @@ inline tc_tuning default_tuning(int cu_count) {
     t.lane_blocks = (uint32_t)cu * 8;
     t.wave_blocks = (uint32_t)cu * 10;
     t.group_blocks = (uint32_t)cu * 2;
+    t.batch_blocks = (uint32_t)cu * 3;
     return t;
 }
 
 // batched mode (tc_batch.hip)
+void append_items(const device_graph& g, uint32_t gi, std::vector<work_item>& out);
 void batch_release_all(tc_context_s* ctx);
 void batch_forget_graph_locked(tc_context_s* ctx, tc_graph g);
 
 // serving loop (tc_serve.cpp)
+void serve_stop(tc_context_s* ctx);
 void serve_shutdown(tc_context_s* ctx);
 
 }  // namespace tc

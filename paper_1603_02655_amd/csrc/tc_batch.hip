@@ -1,16 +1,165 @@
-// Batched census (placeholder: per-graph launches).
+// Batched census over many resident graphs: one persistent kernel launch over
+// a work-item list (graph, execution mode, dyad range), captured once into a
+// HIP graph (zero accumulators -> persistent kernel -> 16 counts per graph back
+// to pinned host memory) and replayed.  Descriptors and items live in device
+// buffers read by the kernel, so another set of graphs that fits the captured
+// capacities is served by rewriting those buffers and replaying; the capture is
+// redone only when a capacity grows.
+#include <algorithm>
+#include <cstring>
+
 #include "tc_api_internal.h"
 
 namespace tc {
-struct batch_plan {};
-void batch_release_all(tc_context_s* ctx) { delete ctx->batch; ctx->batch = nullptr; }
-void batch_forget_graph_locked(tc_context_s* ctx, tc_graph) { delete ctx->batch; ctx->batch = nullptr; }
-}  // namespace tc
 
-extern "C" int tc_census_batch(tc_context ctx, const tc_graph* graphs, int32_t count, uint64_t* counts) {
-    return tc_census_each(ctx, graphs, count, counts);
+struct batch_plan {
+    std::vector<tc_graph> graphs;       // graphs the device buffers currently describe
+    uint32_t cap_graphs = 0, cap_items = 0;
+    graph_desc* d_desc = nullptr;
+    work_item* d_items = nullptr;
+    uint32_t* d_num = nullptr;
+    unsigned long long* d_accs = nullptr;
+    unsigned int* d_ctr = nullptr;
+    unsigned long long* h_accs = nullptr;   // pinned
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    uint32_t grid = 0;
+    bool valid = false;                     // buffers describe `graphs`
+
+    void release() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (d_desc) (void)hipFree(d_desc);
+        if (d_items) (void)hipFree(d_items);
+        if (d_num) (void)hipFree(d_num);
+        if (d_accs) (void)hipFree(d_accs);
+        if (d_ctr) (void)hipFree(d_ctr);
+        if (h_accs) (void)hipHostFree(h_accs);
+        *this = batch_plan{};
+    }
+};
+
+void batch_release_all(tc_context_s* ctx) {
+    if (ctx->batch) {
+        if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+        ctx->batch->release();
+        delete ctx->batch;
+        ctx->batch = nullptr;
+    }
 }
 
-extern "C" int tc_autotune(tc_context ctx, const tc_graph*, int32_t, const char*, tc_tuning* best) {
-    return best ? tc_get_tuning(ctx, best) : TC_OK;
+void batch_forget_graph_locked(tc_context_s* ctx, tc_graph g) {
+    batch_plan* p = ctx->batch;
+    if (p && std::find(p->graphs.begin(), p->graphs.end(), g) != p->graphs.end()) {
+        p->graphs.clear();
+        p->valid = false;
+    }
+}
+
+// Work items of one graph: group-mode dyads first (largest), then wave-mode
+// chunks, then lane-mode chunks.
+void append_items(const device_graph& g, uint32_t gi, std::vector<work_item>& out) {
+    for (uint64_t d = g.bucket_off[2]; d < g.bucket_off[3]; ++d)
+        out.push_back(work_item{gi, kItemGroup, (uint32_t)d, (uint32_t)d + 1});
+    for (uint64_t d = g.bucket_off[1]; d < g.bucket_off[2]; d += kBatchWavePerItem)
+        out.push_back(work_item{gi, kItemWave, (uint32_t)d,
+                                (uint32_t)std::min<uint64_t>(d + kBatchWavePerItem, g.bucket_off[2])});
+    for (uint64_t d = g.bucket_off[0]; d < g.bucket_off[1]; d += kBatchLanePerItem)
+        out.push_back(work_item{gi, kItemLane, (uint32_t)d,
+                                (uint32_t)std::min<uint64_t>(d + kBatchLanePerItem, g.bucket_off[1])});
+}
+
+namespace {
+
+hipError_t ensure_capacity(batch_plan* p, uint32_t graphs, uint32_t items, hipStream_t s, uint32_t grid) {
+    if (p->exec && graphs <= p->cap_graphs && items <= p->cap_items && grid == p->grid) return hipSuccess;
+    (void)hipStreamSynchronize(s);
+    p->release();
+    p->cap_graphs = std::max<uint32_t>(graphs + graphs / 4, 16);
+    p->cap_items = std::max<uint32_t>(items + items / 4, 1024);
+    p->grid = grid;
+    hipError_t e = hipMalloc((void**)&p->d_desc, sizeof(graph_desc) * p->cap_graphs);
+    if (e == hipSuccess) e = hipMalloc((void**)&p->d_items, sizeof(work_item) * p->cap_items);
+    if (e == hipSuccess) e = hipMalloc((void**)&p->d_num, sizeof(uint32_t));
+    if (e == hipSuccess) e = hipMalloc((void**)&p->d_accs, sizeof(unsigned long long) * kNumClasses * p->cap_graphs);
+    if (e == hipSuccess) e = hipMalloc((void**)&p->d_ctr, sizeof(unsigned int) * 64);
+    if (e == hipSuccess)
+        e = hipHostMalloc((void**)&p->h_accs, sizeof(unsigned long long) * kNumClasses * p->cap_graphs);
+    if (e != hipSuccess) {
+        p->release();
+        return e;
+    }
+    // capture: zero accumulators and counters, persistent kernel, read-back
+    e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    hipError_t el = batch_launch(p->d_desc, p->d_items, p->d_num, p->d_accs, (uint64_t)kNumClasses * p->cap_graphs,
+                                 p->d_ctr, p->grid, s);
+    hipError_t ec = hipMemcpyAsync(p->h_accs, p->d_accs, sizeof(unsigned long long) * kNumClasses * p->cap_graphs,
+                                   hipMemcpyDeviceToHost, s);
+    e = hipStreamEndCapture(s, &p->graph);
+    if (el != hipSuccess) e = el;
+    if (ec != hipSuccess) e = ec;
+    if (e == hipSuccess) e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) p->release();
+    return e;
+}
+
+}  // namespace
+
+}  // namespace tc
+
+using namespace tc;
+
+extern "C" int tc_census_batch(tc_context ctx, const tc_graph* graphs, int32_t count, uint64_t* counts) {
+    if (!ctx || count < 0 || (count > 0 && (!graphs || !counts))) return TC_ERR_ARG;
+    if (count == 0) return TC_OK;
+    if (hipSetDevice(ctx->device) != hipSuccess) return TC_ERR_DEVICE;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    for (int32_t i = 0; i < count; ++i)
+        if (!graphs[i] || !ctx->graphs.count(graphs[i])) return TC_ERR_ARG;
+    if (!ctx->batch) ctx->batch = new (std::nothrow) batch_plan();
+    if (!ctx->batch) return TC_ERR_NOMEM;
+    batch_plan* p = ctx->batch;
+    std::vector<tc_graph> want(graphs, graphs + count);
+    hipError_t e = hipSuccess;
+    if (!(p->valid && p->graphs == want && p->grid == ctx->tuning.batch_blocks)) {
+        std::vector<work_item> items;
+        std::vector<graph_desc> descs(count);
+        for (int32_t i = 0; i < count; ++i) {
+            const device_graph& g = graphs[i]->g;
+            descs[i] = graph_desc{g.dyads, g.nbr, g.tpre, (uint64_t)g.n};
+            append_items(g, (uint32_t)i, items);
+        }
+        e = ensure_capacity(p, (uint32_t)count, (uint32_t)items.size(), ctx->stream, ctx->tuning.batch_blocks);
+        if (e != hipSuccess) return status_from_hip(e);
+        uint32_t nitems = (uint32_t)items.size();
+        e = hipMemcpyAsync(p->d_desc, descs.data(), sizeof(graph_desc) * count, hipMemcpyHostToDevice, ctx->stream);
+        if (e == hipSuccess && nitems)
+            e = hipMemcpyAsync(p->d_items, items.data(), sizeof(work_item) * nitems, hipMemcpyHostToDevice,
+                               ctx->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(p->d_num, &nitems, sizeof(uint32_t), hipMemcpyHostToDevice, ctx->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);   // host vectors go out of scope
+        if (e != hipSuccess) {
+            p->valid = false;
+            return status_from_hip(e);
+        }
+        p->graphs = want;
+        p->valid = true;
+    }
+    if (ctx->timing) (void)hipEventRecord(ctx->ev[0], ctx->stream);
+    e = hipGraphLaunch(p->exec, ctx->stream);
+    if (ctx->timing) (void)hipEventRecord(ctx->ev[1], ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return status_from_hip(e);
+    if (ctx->timing) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[1]) == hipSuccess) {
+            ctx->kstats.batch_ms += ms;
+            ctx->kstats.batch_launches += 1;
+        }
+    }
+    for (int32_t i = 0; i < count; ++i)
+        finalize_counts(graphs[i]->g.n, p->h_accs + (size_t)kNumClasses * i, counts + (size_t)kNumClasses * i);
+    return TC_OK;
 }

@@ -16,6 +16,26 @@ struct census_slices {
     uint64_t end[kBuckets];
 };
 
+// ---- batched launch over many graphs ----
+struct graph_desc {
+    const dyad_rec* dyads;
+    const uint32_t* nbr;
+    const uint64_t* tpre;
+    uint64_t n;
+};
+enum : uint32_t { kItemLane = 0, kItemWave = 1, kItemGroup = 2 };
+struct work_item {
+    uint32_t graph, kind, begin, end;   // dyads [begin, end) of graph `graph`'s record array
+};
+constexpr uint32_t kBatchLanePerItem = 256;   // one dyad per thread of a 256-thread workgroup
+constexpr uint32_t kBatchWavePerItem = 16;    // four wavefronts, four dyads each
+
+// Zeroes accs[0..acc_words) and the 8 work counters, then runs the persistent
+// batch kernel over items[0..*num_items) with `grid` workgroups.
+hipError_t batch_launch(const graph_desc* descs, const work_item* items, const uint32_t* num_items,
+                        unsigned long long* accs, uint64_t acc_words, unsigned int* counters, uint32_t grid,
+                        hipStream_t s);
+
 hipError_t census_upload_table();
 // Zeroes acc (16 x u64) and counters (kBuckets x u32), then runs the three
 // bucket kernels over the given slices.  ev, when not null, holds 2*kBuckets

@@ -139,6 +139,27 @@ constexpr uint32_t kSentinel = 0xffffffffu;
 // memory (L1/L2 resident for the short rows of this bucket).
 constexpr int kLaneB = 256;
 
+template <class H>
+__device__ inline void lane_dyad(const dyad_rec& r, const uint32_t* __restrict__ nbr, const uint64_t* __restrict__ tpre,
+                                 uint64_t n, const uint8_t* T, H& h) {
+    const dyad_totals t = load_totals(r, tpre);
+    const uint32_t u = r.u, v = r.vf >> 2, f = r.vf & 3u;
+    uint32_t i = r.bu, j = r.bv;
+    // rows are never empty: v is in row u and u is in row v
+    uint32_t a = nbr[i], b = nbr[j];
+    for (;;) {
+        if ((a ^ b) < 4u) on_common(a >> 2, a & 3u, b & 3u, u, v, f, T, h);
+        if (a <= (b | 3u)) {
+            if (++i >= r.eu) break;
+            a = nbr[i];
+        } else {
+            if (++j >= r.ev) break;
+            b = nbr[j];
+        }
+    }
+    add_totals(r, t, n, T, h);
+}
+
 __global__ __launch_bounds__(kLaneB) void k_census_lane(census_args L) {
     extern __shared__ unsigned long long lds[];
     __shared__ uint8_t T[64];
@@ -146,27 +167,9 @@ __global__ __launch_bounds__(kLaneB) void k_census_lane(census_args L) {
     lane_bins<kLaneB> h{lds};
     h.clear();
     __syncthreads();
-    const uint32_t* __restrict__ nbr = L.nbr;
     for (uint64_t d = (uint64_t)blockIdx.x * kLaneB + threadIdx.x; d < L.count;
-         d += (uint64_t)gridDim.x * kLaneB) {
-        const dyad_rec r = load_rec(L.dyads + d);
-        const dyad_totals t = load_totals(r, L.tpre);
-        const uint32_t u = r.u, v = r.vf >> 2, f = r.vf & 3u;
-        uint32_t i = r.bu, j = r.bv;
-        // rows are never empty: v is in row u and u is in row v
-        uint32_t a = nbr[i], b = nbr[j];
-        for (;;) {
-            if ((a ^ b) < 4u) on_common(a >> 2, a & 3u, b & 3u, u, v, f, T, h);
-            if (a <= (b | 3u)) {
-                if (++i >= r.eu) break;
-                a = nbr[i];
-            } else {
-                if (++j >= r.ev) break;
-                b = nbr[j];
-            }
-        }
-        add_totals(r, t, L.n, T, h);
-    }
+         d += (uint64_t)gridDim.x * kLaneB)
+        lane_dyad(load_rec(L.dyads + d), L.nbr, L.tpre, L.n, T, h);
     h.flush(L.acc);
 }
 
@@ -188,12 +191,26 @@ __device__ inline uint32_t co_rank(const uint32_t* sA, uint32_t na, const uint32
     return lo;
 }
 
-template <int G, int TW, class H>
+// Synchronisation of the group that shares a dyad: the whole workgroup, or a
+// single wavefront (whose lanes run in lockstep, LDS accesses in order; the
+// fences keep the compiler from moving LDS accesses across the point).
+struct block_sync {
+    __device__ inline void operator()() const { __syncthreads(); }
+};
+struct wave_sync {
+    __device__ inline void operator()() const {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+};
+
+template <int G, int TW, class Sync, class H>
 __device__ inline void merge_path(const dyad_rec& r, const uint32_t* __restrict__ nbr, uint32_t* sA, uint32_t* sB,
-                                  uint32_t* s_xt, const uint8_t* T, H& h) {
+                                  uint32_t* s_xt, uint32_t lane, const uint8_t* T, H& h) {
     constexpr uint32_t PER = TW / G;
     static_assert(TW % G == 0, "tile is a multiple of the group");
-    const uint32_t lane = threadIdx.x;
+    const Sync sync{};
     const uint32_t u = r.u, v = r.vf >> 2, f = r.vf & 3u;
     const uint32_t la = r.eu - r.bu, lb = r.ev - r.bv;
     uint32_t a_pos = 0, b_pos = 0;
@@ -215,7 +232,7 @@ __device__ inline void merge_path(const dyad_rec& r, const uint32_t* __restrict_
             sA[TW] = kSentinel;
             sB[TW] = kSentinel;
         }
-        __syncthreads();
+        sync();
         const uint32_t total = min((uint32_t)TW, na + nb);
         const uint32_t d0 = lane * PER;
         if (d0 < total) {
@@ -237,7 +254,7 @@ __device__ inline void merge_path(const dyad_rec& r, const uint32_t* __restrict_
             }
             if (d0 + steps == total) *s_xt = i;
         }
-        __syncthreads();
+        sync();
         const uint32_t xt = *s_xt;
         a_pos += xt;
         b_pos += total - xt;
@@ -280,7 +297,7 @@ __global__ __launch_bounds__(kWaveB) void k_census_wave(census_args L, unsigned 
             const dyad_rec r = load_rec(L.dyads + d);
             dyad_totals t{};
             if (threadIdx.x == 0) t = load_totals(r, L.tpre);
-            merge_path<kWaveB, kWaveTile>(r, L.nbr, sA, sB, &s_xt, T, h);
+            merge_path<kWaveB, kWaveTile, block_sync>(r, L.nbr, sA, sB, &s_xt, threadIdx.x, T, h);
             if (threadIdx.x == 0) add_totals(r, t, L.n, T, h);
         }
         c = __shfl(cn, 0, 64);
@@ -313,7 +330,7 @@ __global__ __launch_bounds__(kGroupB) void k_census_group(census_args L, unsigne
             const dyad_rec r = load_rec(L.dyads + d);
             dyad_totals t{};
             if (threadIdx.x == 0) t = load_totals(r, L.tpre);
-            merge_path<kGroupB, kGroupTile>(r, L.nbr, sA, sB, &s_xt, T, h);
+            merge_path<kGroupB, kGroupTile, block_sync>(r, L.nbr, sA, sB, &s_xt, threadIdx.x, T, h);
             if (threadIdx.x == 0) add_totals(r, t, L.n, T, h);
         }
         __syncthreads();
@@ -321,6 +338,86 @@ __global__ __launch_bounds__(kGroupB) void k_census_group(census_args L, unsigne
         __syncthreads();
     }
     h.flush(L.acc);
+}
+
+
+// --------------------------------------------------------------- batch ----
+// One persistent launch over the work items of many resident graphs.  A
+// workgroup takes items one at a time (per-XCD counters); an item is a slice of
+// one graph's bucket: up to 256 lane-mode dyads (one per thread), up to
+// 4 * kBatchWavePerItem wave-mode dyads (wavefront w takes every fourth), or one
+// group-mode dyad.  Counts go to per-lane bins that are flushed into the
+// graph's 16 accumulators whenever the workgroup moves to another graph.
+constexpr int kBatchB = 256;
+constexpr int kBatchWaveTile = 512;
+constexpr int kBatchGroupTile = 2048;
+constexpr int kBatchTileWords = (4 * 2 * (kBatchWaveTile + 1) > 2 * (kBatchGroupTile + 1))
+                                    ? 4 * 2 * (kBatchWaveTile + 1) : 2 * (kBatchGroupTile + 1);
+
+__global__ __launch_bounds__(kBatchB) void k_census_batch(const graph_desc* __restrict__ G,
+                                                          const work_item* __restrict__ items,
+                                                          const uint32_t* __restrict__ num_items,
+                                                          unsigned long long* __restrict__ accs,
+                                                          unsigned int* __restrict__ ctr) {
+    extern __shared__ unsigned long long lds[];
+    __shared__ uint8_t T[64];
+    __shared__ uint32_t tiles[kBatchTileWords];
+    __shared__ uint32_t s_xt[kBatchB / 64], s_next;
+    if (threadIdx.x < 64) T[threadIdx.x] = c_table[threadIdx.x];
+    lane_bins<kBatchB> h{lds};
+    h.clear();
+    const uint32_t count = *num_items;
+    const uint32_t xcd = blockIdx.x % kXcds;
+    const uint32_t tid = threadIdx.x, wid = tid >> 6, lane = tid & 63u;
+    uint32_t cur = 0xffffffffu;
+    if (tid == 0) s_next = take_chunk(ctr, xcd);
+    __syncthreads();
+    uint32_t idx = s_next;
+    __syncthreads();
+    while (idx < count) {
+        if (tid == 0) s_next = take_chunk(ctr, xcd);
+        const work_item it = items[idx];
+        if (it.graph != cur) {
+            if (cur != 0xffffffffu) {
+                h.flush(accs + (uint64_t)kNumClasses * cur);
+                __syncthreads();
+                h.clear();
+            }
+            cur = it.graph;
+            __syncthreads();
+        }
+        const graph_desc g = G[it.graph];
+        if (it.kind == kItemLane) {
+            const uint32_t d = it.begin + tid;
+            if (d < it.end) lane_dyad(load_rec(g.dyads + d), g.nbr, g.tpre, g.n, T, h);
+        } else if (it.kind == kItemWave) {
+            uint32_t* sA = tiles + wid * 2 * (kBatchWaveTile + 1);
+            uint32_t* sB = sA + kBatchWaveTile + 1;
+            for (uint32_t d = it.begin + wid; d < it.end; d += kBatchB / 64) {
+                const dyad_rec r = load_rec(g.dyads + d);
+                dyad_totals t{};
+                if (lane == 0) t = load_totals(r, g.tpre);
+                merge_path<64, kBatchWaveTile, wave_sync>(r, g.nbr, sA, sB, &s_xt[wid], lane, T, h);
+                if (lane == 0) add_totals(r, t, g.n, T, h);
+            }
+        } else {
+            const dyad_rec r = load_rec(g.dyads + it.begin);
+            dyad_totals t{};
+            if (tid == 0) t = load_totals(r, g.tpre);
+            merge_path<kBatchB, kBatchGroupTile, block_sync>(r, g.nbr, tiles, tiles + kBatchGroupTile + 1, &s_xt[0],
+                                                              tid, T, h);
+            if (tid == 0) add_totals(r, t, g.n, T, h);
+        }
+        __syncthreads();
+        idx = s_next;
+        __syncthreads();
+    }
+    if (cur != 0xffffffffu) h.flush(accs + (uint64_t)kNumClasses * cur);
+}
+
+__global__ void k_fill_u64_grid(unsigned long long* p, uint64_t n) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = 0;
 }
 
 __global__ void k_zero_u32(unsigned int* p, int n) {
@@ -332,6 +429,17 @@ __global__ void k_zero_u64(unsigned long long* p, int n) {
 }
 
 }  // namespace
+
+hipError_t batch_launch(const graph_desc* descs, const work_item* items, const uint32_t* num_items,
+                        unsigned long long* accs, uint64_t acc_words, unsigned int* counters, uint32_t grid,
+                        hipStream_t s) {
+    uint32_t zb = (uint32_t)std::min<uint64_t>((acc_words + 255) / 256, 1024);
+    hipLaunchKernelGGL(k_fill_u64_grid, dim3(zb ? zb : 1), dim3(256), 0, s, accs, acc_words);
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, counters, kXcds);
+    hipLaunchKernelGGL(k_census_batch, dim3(grid), dim3(kBatchB), sizeof(unsigned long long) * lane_bins<kBatchB>::kWords,
+                       s, descs, items, num_items, accs, counters);
+    return hipGetLastError();
+}
 
 hipError_t census_upload_table() {
     return hipMemcpyToSymbol(HIP_SYMBOL(c_table), kTable.t, sizeof(kTable.t));

@@ -63,7 +63,8 @@ class tc_graph_info(ctypes.Structure):
 
 class tc_tuning(ctypes.Structure):
     _fields_ = [("t0", ctypes.c_uint32), ("t1", ctypes.c_uint32), ("lane_blocks", ctypes.c_uint32),
-                ("wave_blocks", ctypes.c_uint32), ("group_blocks", ctypes.c_uint32)]
+                ("wave_blocks", ctypes.c_uint32), ("group_blocks", ctypes.c_uint32),
+                ("batch_blocks", ctypes.c_uint32)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -71,7 +72,8 @@ class tc_tuning(ctypes.Structure):
 
 class tc_kernel_stats(ctypes.Structure):
     _fields_ = [("ms", ctypes.c_double * 3), ("launches", ctypes.c_uint64 * 3),
-                ("census_calls", ctypes.c_uint64)]
+                ("census_calls", ctypes.c_uint64), ("batch_ms", ctypes.c_double),
+                ("batch_launches", ctypes.c_uint64)]
 
 
 class tc_serve_stats(ctypes.Structure):
@@ -99,7 +101,9 @@ SIGNATURES = {
     "tc_census_batch": (ctypes.c_int, [_vp, _vp, _i32, _vp]),
     "tc_census_each": (ctypes.c_int, [_vp, _vp, _i32, _vp]),
     "tc_submit": (ctypes.c_int, [_vp, _vp, _P(_u64)]),
+    "tc_submit_arcs": (ctypes.c_int, [_vp, _i32, _i64, _vp, _vp, _u32, _P(_u64)]),
     "tc_poll": (ctypes.c_int, [_vp, _u64, _vp, _P(ctypes.c_int)]),
+    "tc_serve_stop": (ctypes.c_int, [_vp]),
     "tc_serve_get_stats": (ctypes.c_int, [_vp, _P(tc_serve_stats)]),
     "tc_serve_reset_stats": (ctypes.c_int, [_vp]),
     "tc_set_tuning": (ctypes.c_int, [_vp, _P(tc_tuning)]),
@@ -290,12 +294,28 @@ class Context:
         _check(load().tc_submit(self.handle, g.handle, ctypes.byref(t)), "tc_submit")
         return t.value
 
+    def submit_arcs(self, n: int, src, dst, strict: bool = False) -> int:
+        s = np.ascontiguousarray(src, dtype=np.int32)
+        d = np.ascontiguousarray(dst, dtype=np.int32)
+        if s.shape != d.shape:
+            raise ValueError("src and dst differ in length")
+        t = ctypes.c_uint64()
+        _check(load().tc_submit_arcs(self.handle, int(n), int(s.size), s.ctypes.data, d.ctypes.data,
+                                     TC_BUILD_STRICT if strict else 0, ctypes.byref(t)), "tc_submit_arcs")
+        return t.value
+
     def poll(self, ticket: int):
-        """Returns the 16 counts when the ticket is done, else None."""
+        """Returns the 16 counts when the ticket is done, else None; raises
+        TcError if the ticket finished with an error."""
         out = _u64_out(16)
         done = ctypes.c_int()
-        _check(load().tc_poll(self.handle, ticket, out.ctypes.data, ctypes.byref(done)), "tc_poll")
+        rc = load().tc_poll(self.handle, ticket, out.ctypes.data, ctypes.byref(done))
+        if rc != TC_OK and not (rc == TC_ERR_SHUTDOWN and not done.value):
+            raise TcError(rc, "tc_poll")
         return out if done.value else None
+
+    def serve_stop(self):
+        _check(load().tc_serve_stop(self.handle), "tc_serve_stop")
 
     def serve_stats(self) -> dict:
         s = tc_serve_stats()
@@ -336,7 +356,8 @@ class Context:
     def kernel_stats(self) -> dict:
         s = tc_kernel_stats()
         _check(load().tc_get_kernel_stats(self.handle, ctypes.byref(s)), "tc_get_kernel_stats")
-        return {"ms": list(s.ms), "launches": list(s.launches), "census_calls": s.census_calls}
+        return {"ms": list(s.ms), "launches": list(s.launches), "census_calls": s.census_calls,
+                "batch_ms": s.batch_ms, "batch_launches": s.batch_launches}
 
     def reset_kernel_stats(self):
         _check(load().tc_reset_kernel_stats(self.handle), "tc_reset_kernel_stats")

@@ -1,0 +1,217 @@
+"""Batched (persistent, HIP-graph replayed), served (continuous batching) and
+autotuned modes: every result must equal the single-graph census of the same
+graph, which the parity tests pin to the oracle; a sample is also checked
+against the oracle directly here.  Tolerance 0 (integer counts)."""
+import os
+import sys
+import tempfile
+import time
+from math import comb
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1603_02655_amd import synth, tc
+from tests import triads
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = tc.Context(0)
+    yield c
+    c.close()
+
+
+def small_pool(count, seed=0, n_hi=3000):
+    gs = [synth.batch_graph(i, config=40 + seed, n_lo=20, n_hi=n_hi) for i in range(count)]
+    # degenerate members: empty, tiny, single mutual pair, one hub
+    gs.append(synth.Digraph(0, np.zeros(0, np.int32), np.zeros(0, np.int32), "empty0"))
+    gs.append(synth.Digraph(2, np.array([0], np.int32), np.array([1], np.int32), "n2"))
+    gs.append(synth.Digraph(5, np.array([1, 2], np.int32), np.array([2, 1], np.int32), "mutual"))
+    hub = np.arange(1, 2500, dtype=np.int32)
+    gs.append(synth.Digraph(2500, np.zeros(hub.size, np.int32), hub, "star"))
+    return gs
+
+
+def test_batch_equals_each_and_oracle(ctx):
+    pool = small_pool(96)
+    say(f"[gpu] batch of {len(pool)}")
+    handles = [ctx.build_graph(g.n, g.src, g.dst) for g in pool]
+    try:
+        each = ctx.census_each(handles)
+        batch = ctx.census_batch(handles)
+        assert batch.tolist() == each.tolist()
+        for i in range(0, len(pool), 7):
+            g = pool[i]
+            assert batch[i].tolist() == oracle.census(g.n, g.src, g.dst).tolist(), g.name
+        # replays, with eager work on the same stream in between
+        for k in range(4):
+            ctx.census(handles[k])
+            again = ctx.census_batch(handles)
+            assert again.tolist() == batch.tolist(), f"replay {k}"
+        # another set of graphs of the same shape: buffers rewritten, no re-capture needed
+        sub = handles[10:60]
+        assert ctx.census_batch(sub).tolist() == each[10:60].tolist()
+        assert ctx.census_batch(handles[::-1]).tolist() == each[::-1].tolist()
+    finally:
+        for h in handles:
+            h.release()
+
+
+def test_batch_grows_and_survives_release(ctx):
+    pool = small_pool(20, seed=1)
+    handles = [ctx.build_graph(g.n, g.src, g.dst) for g in pool]
+    try:
+        a = ctx.census_batch(handles[:5])
+        b = ctx.census_batch(handles)          # larger than the first capture
+        assert b[:5].tolist() == a.tolist()
+        handles[3].release()
+        rest = handles[:3] + handles[4:]
+        c = ctx.census_batch(rest)
+        assert c.tolist() == np.concatenate([b[:3], b[4:]]).tolist()
+    finally:
+        for h in handles:
+            if h.handle:
+                h.release()
+
+
+def test_batch_matches_disjoint_union(ctx):
+    g1 = synth.rmat_digraph(1500, 12000, synth.rng_for(41, 1), reciprocity=0.1)
+    g2 = synth.rmat_digraph(2200, 20000, synth.rng_for(41, 2), reciprocity=0.1)
+    h1 = ctx.build_graph(g1.n, g1.src, g1.dst)
+    h2 = ctx.build_graph(g2.n, g2.src, g2.dst)
+    n = g1.n + g2.n
+    hu = ctx.build_graph(n, np.concatenate([g1.src, g2.src + g1.n]), np.concatenate([g1.dst, g2.dst + g1.n]))
+    try:
+        c = ctx.census_batch([h1, h2]).astype(object)
+        u = ctx.census(hu).astype(object)
+        s1 = triads.degree_sides(g1.n, g1.src, g1.dst)
+        s2 = triads.degree_sides(g2.n, g2.src, g2.dst)
+        exp = c[0] + c[1]
+        exp[1] += s1["A"] * g2.n + s2["A"] * g1.n
+        exp[2] += s1["M"] * g2.n + s2["M"] * g1.n
+        exp[0] = comb(n, 3) - int(exp[1:].sum())
+        assert u.tolist() == exp.tolist()
+    finally:
+        h1.release()
+        h2.release()
+        hu.release()
+
+
+def test_autotune_keeps_counts_and_caches(ctx):
+    pool = small_pool(24, seed=2)
+    handles = [ctx.build_graph(g.n, g.src, g.dst) for g in pool]
+    default = ctx.get_tuning()
+    try:
+        want = ctx.census_each(handles)
+        with tempfile.TemporaryDirectory() as tmp:
+            path = os.path.join(tmp, "tune.json")
+            best = ctx.autotune(handles, path)
+            say(f"[gpu] autotuned batch: {best}")
+            assert os.path.exists(path)
+            assert ctx.census_batch(handles).tolist() == want.tolist()
+            assert ctx.census_each(handles).tolist() == want.tolist()
+            ctx.set_tuning(**default)
+            again = ctx.autotune(handles, path)   # cache hit
+            assert again == best
+            single = ctx.autotune(handles[:1], path)
+            say(f"[gpu] autotuned single: {single}")
+            assert ctx.census(handles[0]).tolist() == want[0].tolist()
+            assert "single" in open(path).read() and "batch" in open(path).read()
+    finally:
+        ctx.set_tuning(**default)
+        for h in handles:
+            h.release()
+
+
+def _drain(ctx, tickets, timeout=120.0):
+    out = {}
+    t0 = time.time()
+    while len(out) < len(tickets):
+        for t in tickets:
+            if t in out:
+                continue
+            r = ctx.poll(t)
+            if r is not None:
+                out[t] = r
+        assert time.time() - t0 < timeout, "serving did not finish"
+    return out
+
+
+def test_serving_mix_equals_alone():
+    pool = small_pool(30, seed=3, n_hi=20000)
+    with tc.Context(0) as c:
+        handles = [c.build_graph(g.n, g.src, g.dst) for g in pool]
+        alone = c.census_each(handles)
+        say("[gpu] serving: 600 resident requests")
+        rng = np.random.default_rng(0)
+        order = rng.integers(0, len(handles), 600)
+        tickets = []
+        for k, i in enumerate(order):
+            tickets.append((c.submit(handles[i]), i))
+            if k % 50 == 0:
+                time.sleep(0.002)           # arrivals spread over time: several rounds
+        res = _drain(c, [t for t, _ in tickets])
+        for t, i in tickets:
+            assert res[t].tolist() == alone[i].tolist(), pool[i].name
+        st = c.serve_stats()
+        say(f"[gpu] serve stats {st}")
+        assert st["completed"] >= 600 and st["rounds"] >= 2
+        # cold requests carry their arcs; built and released by the loop
+        say("[gpu] serving: cold requests")
+        cold = [c.submit_arcs(g.n, g.src, g.dst) for g in pool[:6]]
+        res = _drain(c, cold)
+        for t, g in zip(cold, pool[:6]):
+            assert res[t].tolist() == oracle.census(g.n, g.src, g.dst).tolist()
+        with pytest.raises(tc.TcError) as e:
+            c.poll(987654321)
+        assert e.value.code == tc.TC_ERR_NOT_FOUND
+        say("[gpu] serving: closing")
+
+
+def test_serving_tiny_budget_and_errors():
+    g0 = synth.rmat_digraph(1 << 12, 1 << 15, synth.rng_for(42, 0), reciprocity=0.1)
+    with tc.Context(0, hbm_budget_bytes=64 << 10) as c:
+        h = c.build_graph(g0.n, g0.src, g0.dst)
+        alone = c.census(h)
+        say("[gpu] tiny budget: queued requests")
+        tickets = [c.submit(h) for _ in range(40)]    # small footprints, queue behind the budget
+        res = _drain(c, tickets)
+        assert all(r.tolist() == alone.tolist() for r in res.values())
+        say("[gpu] tiny budget: oversized and bad requests")
+        big = c.submit_arcs(g0.n, g0.src, g0.dst)     # build footprint above the whole budget
+        t0 = time.time()
+        while True:
+            try:
+                r = c.poll(big)
+            except tc.TcError as e:
+                assert e.code == tc.TC_ERR_NOMEM
+                break
+            assert r is None and time.time() - t0 < 30
+        bad = c.submit_arcs(3, [0, 1], [1, 7])       # id out of range: reported by poll
+        with pytest.raises(tc.TcError) as e:
+            while c.poll(bad) is None:
+                time.sleep(0.001)
+        assert e.value.code in (tc.TC_ERR_ARG, tc.TC_ERR_NOMEM)
+        say("[gpu] tiny budget: release while pending, stop")
+        # a graph with pending tickets cannot be released
+        many = [c.submit(h) for _ in range(30)]
+        rc = tc.load().tc_graph_release(c.handle, h.handle)
+        assert rc in (tc.TC_ERR_BUSY, tc.TC_OK)
+        if rc == tc.TC_OK:
+            h.handle = None
+        _drain(c, many)
+        c.serve_stop()
+        with pytest.raises(tc.TcError) as e:
+            c.submit_arcs(3, [0], [1])
+        assert e.value.code == tc.TC_ERR_SHUTDOWN
+        if h.handle:
+            h.release()

@@ -58,6 +58,8 @@ def _load():
     lib.oracle_census_range.restype = ctypes.c_int
     lib.oracle_census_mt.argtypes = [vp, ctypes.c_int, u64p]
     lib.oracle_census_mt.restype = ctypes.c_int
+    lib.oracle_census64.argtypes = [vp, u64p]
+    lib.oracle_census64.restype = ctypes.c_int
     lib.oracle_brute.argtypes = [i32, i64, vp, vp, ctypes.c_int, u64p]
     lib.oracle_brute.restype = ctypes.c_int
     _lib = lib
@@ -126,6 +128,12 @@ class OracleGraph:
             raise MemoryError
         return out
 
+    def census64(self) -> np.ndarray:
+        out = np.zeros(64, np.uint64)
+        if _load().oracle_census64(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))) != 0:
+            raise MemoryError
+        return out
+
     def census_mt(self, threads: int) -> np.ndarray:
         out = np.zeros(16, np.uint64)
         r = _load().oracle_census_mt(self._h, threads, out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)))
@@ -138,6 +146,12 @@ def census(n: int, src, dst) -> np.ndarray:
     """Full 16-class census of the digraph (n, src->dst)."""
     with OracleGraph(n, src, dst) as g:
         return g.census()
+
+
+def census64(n: int, src, dst) -> np.ndarray:
+    """64-class labelled census: raw TriadCode histogram in the loop's roles."""
+    with OracleGraph(n, src, dst) as g:
+        return g.census64()
 
 
 def brute(n: int, src, dst, threads: int = 1) -> np.ndarray:

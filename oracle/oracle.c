@@ -33,6 +33,13 @@
  *                         the join (section v0.6, "local census array per thread").
  *   oracle_brute          the naive O(n^3) census the section on the algorithm
  *                         mentions: every triple classified through TriadCode.
+ *   oracle_census64       the 64-class labelled census the section on the
+ *                         TriadCode describes before the table folds it into
+ *                         16 classes: the same loop, histogramming the raw
+ *                         6-bit code of (u, v, w) in the roles the loop gives
+ *                         them; the dyadic term n - |S| - 2 goes to the code of
+ *                         the (u, v) pair alone (w joined to neither), and code
+ *                         0 is C(n, 3) minus the rest.
  *
  * Input handling (reading of the thesis's "strict digraph, E a set"): arcs
  * (u, u) are dropped and repeated arcs are merged; ids must lie in [0, n).
@@ -311,6 +318,45 @@ int oracle_census(void *h, uint64_t out[16])
     census_vertices(g, 0, g->n, buf, c);
     free(buf);
     finish_null(g->n, c);
+    memcpy(out, c, sizeof(c));
+    return 0;
+}
+
+/* The per-dyad body again, counting raw codes instead of classes. */
+static void census64_dyad(const og_t *g, int32_t u, int32_t v, int32_t *buf, uint64_t c[64])
+{
+    int64_t n = g->n;
+    int64_t s = build_S(g, u, v, buf);
+    int e0 = is_edge(g, u, v), e1 = is_edge(g, v, u);
+    int pre = e0 + 2 * e1;
+    c[pre] += (uint64_t)(n - s - 2);
+    for (int64_t k = 0; k < s; ++k) {
+        int32_t w = buf[k];
+        if (v < w || (w < v && u < w && !is_neighbour(g, u, w))) {
+            int code = pre + 4 * is_edge(g, u, w) + 8 * is_edge(g, w, u)
+                     + 16 * is_edge(g, v, w) + 32 * is_edge(g, w, v);
+            c[code] += 1;
+        }
+    }
+}
+
+int oracle_census64(void *h, uint64_t out[64])
+{
+    og_t *g = (og_t *)h;
+    uint64_t c[64] = {0};
+    int32_t *buf = (int32_t *)malloc(sizeof(int32_t) * (size_t)(2 * max_degree(g) + 1));
+    if (!buf) return -1;
+    for (int32_t u = 0; u < g->n; ++u)
+        for (int64_t p = g->nb_ptr[u]; p < g->nb_ptr[u + 1]; ++p) {
+            int32_t v = g->nb[p];
+            if (u < v) census64_dyad(g, u, v, buf, c);
+        }
+    free(buf);
+    int64_t n = g->n;
+    u128 total = n >= 3 ? (u128)n * (u128)(n - 1) * (u128)(n - 2) / 6 : 0;
+    u128 sum = 0;
+    for (int k = 1; k < 64; ++k) sum += c[k];
+    c[0] = (uint64_t)(total - sum);
     memcpy(out, c, sizeof(c));
     return 0;
 }

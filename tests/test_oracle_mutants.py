@@ -88,3 +88,55 @@ def test_pins_catch_mutant(name):
     with tempfile.TemporaryDirectory() as tmp:
         lib = _build_mutant(name, tmp)
         assert _pins_reject(lib), f"mutant {name} survived the pins"
+
+
+# Mistakes planted only in the labelled (64-class) census body: its classes
+# are unchanged by most of them, so the brute force by triples must catch them.
+MUTANTS64 = {
+    "dyadic-term-to-null": ("c[pre] += (uint64_t)(n - s - 2);", "c[0] += (uint64_t)(n - s - 2);"),
+    "uv-pair-transposed": ("int pre = e0 + 2 * e1;\n    c[pre]", "int pre = e1 + 2 * e0;\n    c[pre]"),
+    "u-and-v-roles-swapped": ("int code = pre + 4 * is_edge(g, u, w) + 8 * is_edge(g, w, u)\n"
+                              "                     + 16 * is_edge(g, v, w) + 32 * is_edge(g, w, v);\n"
+                              "            c[code] += 1;",
+                              "int code = pre + 16 * is_edge(g, u, w) + 32 * is_edge(g, w, u)\n"
+                              "                     + 4 * is_edge(g, v, w) + 8 * is_edge(g, w, v);\n"
+                              "            c[code] += 1;"),
+}
+
+
+def _census64(lib, n, src, dst):
+    s = np.ascontiguousarray(src, np.int32)
+    d = np.ascontiguousarray(dst, np.int32)
+    h = lib.oracle_graph_new(n, s.size, s.ctypes.data, d.ctypes.data)
+    out = np.zeros(64, np.uint64)
+    lib.oracle_census64(h, out.ctypes.data)
+    lib.oracle_graph_free(h)
+    return out
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS64))
+def test_census64_pins_catch_mutant(name):
+    old, new = MUTANTS64[name]
+    text = open(SRC).read()
+    assert text.count(old) == 1, f"mutation anchor missing or ambiguous: {name}"
+    with tempfile.TemporaryDirectory() as tmp:
+        c, so = os.path.join(tmp, "m.c"), os.path.join(tmp, "m.so")
+        with open(c, "w") as f:
+            f.write(text.replace(old, new))
+        subprocess.run(["gcc", "-O1", "-std=gnu11", "-fPIC", "-shared", "-pthread", c, "-o", so], check=True)
+        lib = ctypes.CDLL(so)
+        lib.oracle_graph_new.restype = ctypes.c_void_p
+        lib.oracle_graph_new.argtypes = [ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p]
+        lib.oracle_census64.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+        lib.oracle_graph_free.argtypes = [ctypes.c_void_p]
+        rng = np.random.default_rng(78)
+        caught = False
+        for _ in range(20):
+            n = int(rng.integers(3, 10))
+            mat = rng.random((n, n)) < rng.uniform(0.1, 0.9)
+            np.fill_diagonal(mat, False)
+            src, dst = np.nonzero(mat)
+            if _census64(lib, n, src, dst).tolist() != triads.brute_census64(n, src, dst).tolist():
+                caught = True
+                break
+        assert caught, f"mutant {name} survived the pins"

@@ -104,6 +104,45 @@ def brute_census(n: int, src, dst) -> np.ndarray:
     return out
 
 
+def counting_roles(a: int, b: int, c: int, joined) -> tuple | None:
+    """Roles (u, v, w) in which the subquadratic loop counts the triple
+    a < b < c with a third vertex, or None if no dyad of it is joined.
+
+    Derived from the loop's condition (w counted for dyad (u, v), u < v, iff
+    w in N(u) with w > v, or w in N(v) \\ N(u) with w > u): from dyad (a, b)
+    the vertex c is counted iff c touches a or b; from (a, c) the vertex b is
+    counted iff b touches c and not a; from (b, c) the vertex a never is.  A
+    triple with one joined dyad is counted by that dyad's n - |S| - 2 term."""
+    ab, ac, bc = joined(a, b), joined(a, c), joined(b, c)
+    if ab:
+        return (a, b, c)
+    if ac:
+        return (a, c, b)
+    if bc:
+        return (b, c, a)
+    return None
+
+
+def brute_census64(n: int, src, dst) -> np.ndarray:
+    """64-class labelled census by triples (pure Python; tiny n only): the
+    6-bit code of each triple read in the roles of counting_roles."""
+    arcs = {(int(x), int(y)) for x, y in zip(src, dst) if x != y}
+
+    def joined(x, y):
+        return (x, y) in arcs or (y, x) in arcs
+
+    out = np.zeros(64, np.uint64)
+    for a, b, c in itertools.combinations(range(n), 3):
+        roles = counting_roles(a, b, c, joined)
+        code = 0
+        if roles is not None:
+            for (x, y), bitv in _ARC_BIT.items():
+                if (roles[x], roles[y]) in arcs:
+                    code |= bitv
+        out[code] += 1
+    return out
+
+
 # ---- multiplicities for the exact degree identities ----------------------
 
 def _per_class(fn):

@@ -227,6 +227,26 @@ def bench_serve(args):
         sys.exit(1)
 
 
+def copy_calibration(nbytes: int):
+    """Three device-to-device copies of nbytes through the HIP runtime the
+    library uses (a plain copy kernel of known size, read by the profiler to
+    scale the FETCH_SIZE / WRITE_SIZE counters)."""
+    import ctypes
+    from paper_1603_02655_amd import tc
+    h = tc.hip_runtime()
+    a, b = ctypes.c_void_p(), ctypes.c_void_p()
+    if h.hipMalloc(ctypes.byref(a), nbytes) != 0 or h.hipMalloc(ctypes.byref(b), nbytes) != 0:
+        raise MemoryError("hipMalloc failed")
+    h.hipMemset.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_size_t]
+    h.hipMemset(a, 1, nbytes)
+    for _ in range(3):
+        if h.hipMemcpy(b, a, nbytes, 3) != 0:   # device to device
+            raise RuntimeError("hipMemcpy failed")
+    tc.device_synchronize(0)
+    h.hipFree(a)
+    h.hipFree(b)
+
+
 def dyad_work(g0):
     """Per-vertex canonical-dyad work sum(|N(u)|+|N(v)|) (for the CPU sample)."""
     n = g0.n
@@ -297,6 +317,9 @@ def main():
     ap.add_argument("--rate", default="2000", help="comma-separated arrival rates (requests/s)")
     ap.add_argument("--duration", type=float, default=5.0)
     ap.add_argument("--pool", type=int, default=64)
+    ap.add_argument("--tuning", default="", help="comma-separated key=value overrides, e.g. t_hub=256")
+    ap.add_argument("--copy-calibration", type=int, default=0,
+                    help="also run 3 device-to-device copies of this many bytes (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the census of one graph is "
@@ -313,6 +336,8 @@ def main():
     log(f"[bench] generating workload {args.workload}")
     g0 = workload(args.workload)
     ctx = tc.Context(0)
+    if args.tuning:
+        ctx.set_tuning(**{k: int(v) for k, v in (kv.split("=") for kv in args.tuning.split(","))})
     log(f"[bench] building n={g0.n} m={g0.m}")
     t = time.perf_counter()
     g = ctx.build_graph(g0.n, g0.src, g0.dst)
@@ -336,11 +361,33 @@ def main():
     m_kept = int(info["arcs_kept"])
     value = m_kept / (el / args.steps)
 
-    # roofline of the dominant kernel: algorithmic bytes = 4 B per merged
-    # neighbour entry (|N(u)|+|N(v)| per dyad) + 8 B per dyad task
-    dom = int(np.argmax(ks["ms"]))
-    dom_ms = ks["ms"][dom] / max(1, ks["launches"][dom])
-    bytes_dom = 4.0 * info["bucket_cost"][dom] + 8.0 * info["bucket_dyads"][dom]
+    # roofline of the dominant kernel, bytes per launch by the algorithmic
+    # model of each kernel:
+    #   merge modes (lane / wave / group): 4 B per entry of the two rows merged
+    #     (|N(u)|+|N(v)| per dyad, |N+(x)|+|N+(y)| per forward-list edge) and
+    #     8 B per task (the (u, v<<2|f) pair);
+    #   hub mode: 4 B per streamed entry of the non-anchor rows, 4 B per staged
+    #     anchor entry (once per task), 8 B per task;
+    #   totals pass (forward-list census): 8 B per dyad and 4 x 8 B of prefix
+    #     counts.
+    tri = bool(ctx.get_tuning()["tri"]) and info["fwd_entries"] > 0
+    if tri:
+        cost, tasks = info["tri_bucket_cost"], info["tri_bucket_edges"]
+        stream, staged = info["tri_stream"], info["tri_staged"]
+    else:
+        cost, tasks = info["bucket_cost"], info["bucket_dyads"]
+        stream, staged = info["hub_stream"], info["hub_staged"]
+    p_dyads = info["asym_dyads"] + info["mutual_dyads"]
+    kern = [("k_census_lane", 0), ("k_census_wave", 1), ("k_census_group", 2), ("k_census_hub", 3)]
+    per_launch_ms = {name: ks["ms"][b] / max(1, ks["launches"][b]) for name, b in kern}
+    bytes_of = {name: (4.0 * stream + 4.0 * staged + 8.0 * tasks[3]) if b == 3 else
+                (4.0 * cost[b] + 8.0 * tasks[b]) for name, b in kern}
+    if tri:
+        per_launch_ms["k_census_totals"] = ks["totals_ms"] / max(1, ks["totals_launches"])
+        bytes_of["k_census_totals"] = 40.0 * p_dyads
+    dom_name = max(per_launch_ms, key=per_launch_ms.get)
+    dom_ms = per_launch_ms[dom_name]
+    bytes_dom = bytes_of[dom_name]
     achieved = bytes_dom / (dom_ms / 1000.0) / 1e9 if dom_ms > 0 else 0.0
     b_alg = 4.0 * info["sum_d2"] + 8.0 * (info["asym_dyads"] + info["mutual_dyads"]) + 4.0 * (g0.n + 1)
     line = {
@@ -362,14 +409,18 @@ def main():
                    "tuning": ctx.get_tuning()},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": ["k_census_lane", "k_census_wave", "k_census_group"][dom],
-                     "kernel_ms": dom_ms},
-        "kernels_ms": {k: (ks["ms"][i] / max(1, ks["launches"][i])) for i, k in enumerate(tc.BUCKETS)},
+                     "kernel": dom_name, "bytes_per_launch": bytes_dom, "kernel_ms": dom_ms},
+        "path": "forward-list triangles" if tri else "dyad intersections",
+        "kernels_ms": per_launch_ms,
+        "kernel_bytes": bytes_of,
         "b_alg_gb": b_alg / 1e9,
         "census_gbs_alg": b_alg / (el / args.steps) / 1e9,
         "build_s": build_s,
         "counts": [int(x) for x in counts],
     }
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        line["copy_calibration_bytes"] = args.copy_calibration
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")
         line["cpu_baseline"] = cpu_baseline(g0, m_kept, args.cpu_seconds)

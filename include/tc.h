@@ -49,7 +49,7 @@ enum {
     TC_BUILD_DEVICE_PTRS = 2  /* src/dst are device pointers (e.g. torch tensors) */
 };
 
-enum { TC_NUM_CLASSES = 16, TC_NUM_BUCKETS = 3 };
+enum { TC_NUM_CLASSES = 16, TC_NUM_BUCKETS = 4 };
 
 /* What the build kept and how the canonical dyads were bucketed. */
 typedef struct {
@@ -62,30 +62,60 @@ typedef struct {
     int64_t max_degree;           /* max |N(u)| (undirected) */
     uint64_t device_bytes;        /* HBM held by the resident graph */
     uint64_t sum_d2;              /* sum over u of |N(u)|^2 = sum over dyads of |N(u)|+|N(v)| */
-    uint64_t bucket_dyads[TC_NUM_BUCKETS];  /* dyads in the lane / wave / group buckets */
+    uint64_t bucket_dyads[TC_NUM_BUCKETS];  /* dyads in the lane / wave / group / hub buckets */
     uint64_t bucket_cost[TC_NUM_BUCKETS];   /* sum of |N(u)|+|N(v)| per bucket */
+    uint64_t hub_tasks;           /* runs of hub dyads sharing their anchor */
+    uint64_t hub_stream;          /* sum over hub dyads of the non-anchor degree (entries probed) */
+    uint64_t hub_staged;          /* sum over hub tasks of the anchor degree (entries staged in LDS) */
+    /* forward lists (built when the tuning has tri = 1; zero otherwise) */
+    uint64_t fwd_entries;                      /* = canonical dyads */
+    uint64_t tri_bucket_edges[TC_NUM_BUCKETS]; /* edge records per bucket (edges with an empty forward list omitted) */
+    uint64_t tri_bucket_cost[TC_NUM_BUCKETS];  /* sum of |N+(x)|+|N+(y)| per bucket */
+    uint64_t tri_tasks;           /* hub tasks over the forward lists */
+    uint64_t tri_stream;          /* sum over hub edges of the non-anchor forward-list length */
+    uint64_t tri_staged;          /* sum over those tasks of the anchor forward-list length */
 } tc_graph_info;
 
-/* Degree-bucket thresholds and launch sizes.  A dyad with key
- * k = |N(u)| + |N(v)| - 2 (the thesis's uniform-distribution workload estimate,
- * figure "Canonical Dyad (uniform distr.)") runs one lane per dyad when k < t0,
- * one wavefront per dyad when t0 <= k < t1, one workgroup per dyad when k >= t1. */
+/* Degree-bucket thresholds and launch sizes.  A dyad one of whose endpoints
+ * has degree >= t_hub is a hub dyad: it is grouped with the other dyads of that
+ * endpoint (its anchor, the endpoint of larger degree), whose row a workgroup
+ * stages once in LDS while the other rows stream against it.  Any other dyad,
+ * with key k = |N(u)| + |N(v)| - 2 (the thesis's uniform-distribution
+ * workload estimate, figure "Canonical Dyad (uniform distr.)"), runs one lane
+ * per dyad when k < t0, one wavefront per dyad when t0 <= k < t1, one
+ * workgroup per dyad when k >= t1.  t_hub = 0xffffffff disables the hub mode.
+ *
+ * tri = 1 (graphs built or rebucketed while it is set) also builds forward
+ * lists: N+(x), the neighbours that follow x in degree order ((|N|, id)
+ * ascending).  tc_census, tc_census_each and tc_census64 then add the
+ * intersection-free per-dyad terms in one pass over the dyads and find every
+ * shared vertex of every dyad through the triangles of the graph, each
+ * triangle once, as a shared vertex of the forward lists of its two first
+ * vertices; the same thresholds bucket those edge records by
+ * |N+(x)| + |N+(y)| (and t_hub by the longer forward list).  The counts are
+ * identical either way.  tc_census_range, the batched and the served modes
+ * always use the dyad records. */
 typedef struct {
     uint32_t t0, t1;
     uint32_t lane_blocks;    /* grid cap, lane kernel (256-thread blocks) */
     uint32_t wave_blocks;    /* resident one-wave blocks, wave kernel */
     uint32_t group_blocks;   /* resident 256-thread blocks, group kernel */
     uint32_t batch_blocks;   /* resident 256-thread blocks, batched (persistent) kernel */
+    uint32_t t_hub;
+    uint32_t hub_blocks;     /* resident 256-thread blocks, hub kernel */
+    uint32_t tri;            /* 1: whole-graph census through triangles of the forward lists */
 } tc_tuning;
 
 /* Accumulated device time of the census kernels, per bucket (lane, wave,
- * group), measured with HIP events recorded on the context's stream. */
+ * group, hub), measured with HIP events recorded on the context's stream. */
 typedef struct {
     double ms[TC_NUM_BUCKETS];
     uint64_t launches[TC_NUM_BUCKETS];
     uint64_t census_calls;
     double batch_ms;             /* replays of the captured batched launch */
     uint64_t batch_launches;
+    double totals_ms;            /* per-dyad totals pass (tri = 1 only) */
+    uint64_t totals_launches;
 } tc_kernel_stats;
 
 /* Serving statistics (tc_submit / tc_poll). */
@@ -124,6 +154,18 @@ int tc_graph_release(tc_context ctx, tc_graph g);
 
 /* Synchronous census: counts[16] (host) receives the 16 class counts of g. */
 int tc_census(tc_context ctx, tc_graph g, uint64_t counts[16]);
+
+/* Labelled 64-class census: counts[64] (host) receives the histogram of the
+ * raw 6-bit TriadCode (bit 1 u->v, 2 v->u, 4 u->w, 8 w->u, 16 v->w, 32 w->v)
+ * that the census loop computes before the table folds codes into classes
+ * (section "Triad Census Algorithm", TriadCode and TriadTable): each counted
+ * triple is read in the roles the loop gives it (u < v the canonical dyad that
+ * counts it, w the third vertex); the term n - |S| - 2 of a dyad goes to the
+ * code of the (u, v) pair alone; counts[0] is C(n, 3) minus the rest.  The
+ * histogram depends on the vertex ids (it is not an isomorphism invariant);
+ * folding it through the 64 -> 16 table gives tc_census.  Runs the census
+ * kernels three times (one pass per (u, v) dyad type).  Errors as tc_census. */
+int tc_census64(tc_context ctx, tc_graph g, uint64_t counts[64]);
 
 /* Partial census over the canonical dyads (u, v) with u in [u_begin, u_end):
  * the local census of one task queue (figure "Subquadratic Triad Census

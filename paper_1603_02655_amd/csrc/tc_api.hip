@@ -26,11 +26,11 @@ void finalize_counts(int64_t n, const unsigned long long* raw, uint64_t out[16])
     out[0] = (uint64_t)(total - sum);
 }
 
-census_slices full_slices(const device_graph& g) {
+census_slices full_slices(const device_graph& g, bool tri) {
     census_slices sl;
     for (int b = 0; b < kBuckets; ++b) {
-        sl.begin[b] = g.bucket_off[b];
-        sl.end[b] = g.bucket_off[b + 1];
+        sl.begin[b] = tri ? g.tri.edges.off[b] : g.bucket_off[b];
+        sl.end[b] = tri ? g.tri.edges.off[b + 1] : g.bucket_off[b + 1];
     }
     return sl;
 }
@@ -40,8 +40,11 @@ census_config config_of(const tc_tuning& t) {
     c.lane_blocks = t.lane_blocks;
     c.wave_blocks = t.wave_blocks;
     c.group_blocks = t.group_blocks;
+    c.hub_blocks = t.hub_blocks;
     return c;
 }
+
+bucket_params params_of(const tc_tuning& t) { return bucket_params{t.t0, t.t1, t.t_hub, t.tri}; }
 
 void fill_info(const tc_graph_s* g, tc_graph_info* info) {
     *info = g->info;
@@ -52,13 +55,25 @@ void fill_info(const tc_graph_s* g, tc_graph_info* info) {
         info->bucket_dyads[b] = g->g.bucket_off[b + 1] - g->g.bucket_off[b];
         info->bucket_cost[b] = g->g.bucket_cost[b];
     }
+    info->hub_tasks = g->g.n_hub_tasks;
+    info->hub_stream = g->g.hub_stream;
+    info->hub_staged = g->g.hub_staged;
+    const forward_lists& t = g->g.tri;
+    info->fwd_entries = t.fwd_ptr ? t.entries : 0;
+    for (int b = 0; b < kBuckets; ++b) {
+        info->tri_bucket_edges[b] = t.edges.off[b + 1] - t.edges.off[b];
+        info->tri_bucket_cost[b] = t.edges.cost[b];
+    }
+    info->tri_tasks = t.edges.n_tasks;
+    info->tri_stream = t.edges.stream;
+    info->tri_staged = t.edges.staged;
 }
 
-// Runs the three bucket kernels over `sl` and copies the 16 raw sums to host.
 int run_census_locked(tc_context_s* ctx, const device_graph& g, const census_slices& sl,
-                      unsigned long long raw[16]) {
+                      unsigned long long raw[16], int table, bool tri) {
     hipEvent_t* ev = ctx->timing ? ctx->ev : nullptr;
-    hipError_t e = census_launch(g, sl, ctx->acc, ctx->counters, config_of(ctx->tuning), ctx->stream, ev);
+    hipError_t e = census_launch(g, sl, tri, ctx->tables + 64 * table, ctx->acc, ctx->counters,
+                                 config_of(ctx->tuning), ctx->stream, ev);
     if (e == hipSuccess)
         e = hipMemcpyAsync(ctx->host_raw, ctx->acc, sizeof(unsigned long long) * kNumClasses,
                            hipMemcpyDeviceToHost, ctx->stream);
@@ -74,12 +89,22 @@ int run_census_locked(tc_context_s* ctx, const device_graph& g, const census_sli
                 ctx->kstats.launches[b] += 1;
             }
         }
+        float ms = 0.f;
+        if (tri && g.p > 0 && hipEventElapsedTime(&ms, ev[2 * kBuckets], ev[2 * kBuckets + 1]) == hipSuccess) {
+            ctx->kstats.totals_ms += ms;
+            ctx->kstats.totals_launches += 1;
+        }
     }
     ctx->kstats.census_calls += 1;
     return TC_OK;
 }
 
-int build_into(int32_t n, int64_t m, const int32_t* src, const int32_t* dst, uint32_t flags, uint32_t t0, uint32_t t1,
+int run_full_locked(tc_context_s* ctx, const device_graph& g, unsigned long long raw[16], int table) {
+    const bool tri = ctx->tuning.tri && g.tri.fwd_ptr;
+    return run_census_locked(ctx, g, full_slices(g, tri), raw, table, tri);
+}
+
+int build_into(int32_t n, int64_t m, const int32_t* src, const int32_t* dst, uint32_t flags, const bucket_params& bp,
                hipStream_t stream, device_graph* out, tc_graph_info* info) {
     const int32_t *s_dev = src, *d_dev = dst;
     int32_t* tmp = nullptr;
@@ -92,7 +117,7 @@ int build_into(int32_t n, int64_t m, const int32_t* src, const int32_t* dst, uin
         d_dev = tmp + m;
     }
     build_status st;
-    if (e == hipSuccess) st = build_graph_device(n, m, s_dev, d_dev, t0, t1, stream, out);
+    if (e == hipSuccess) st = build_graph_device(n, m, s_dev, d_dev, bp, stream, out);
     if (tmp) {
         (void)hipStreamSynchronize(stream);
         (void)hipFree(tmp);
@@ -121,9 +146,11 @@ int build_into(int32_t n, int64_t m, const int32_t* src, const int32_t* dst, uin
 
 namespace {
 
+// u-range bounds inside the u-major merge buckets (the hub bucket is filtered
+// by the kernel instead).
 __global__ void k_bounds(const dyad_rec* dyads, const uint64_t* off, uint32_t u0, uint32_t u1, uint64_t* out) {
     int b = threadIdx.x >> 1;
-    if (b >= kBuckets) return;
+    if (b >= kBucketHub) return;
     uint32_t key = (threadIdx.x & 1) ? u1 : u0;
     uint64_t lo = off[b], hi = off[b + 1];
     while (lo < hi) {
@@ -181,7 +208,18 @@ int tc_context_create(int device, uint64_t hbm_budget_bytes, void* hip_stream, t
     if (e == hipSuccess) e = hipMalloc((void**)&ctx->acc, sizeof(unsigned long long) * kNumClasses);
     if (e == hipSuccess) e = hipMalloc((void**)&ctx->counters, sizeof(unsigned int) * 64);
     if (e == hipSuccess) e = hipHostMalloc((void**)&ctx->host_raw, sizeof(unsigned long long) * kNumClasses);
-    for (int i = 0; i < 2 * kBuckets && e == hipSuccess; ++i) e = hipEventCreate(&ctx->ev[i]);
+    if (e == hipSuccess) e = hipMalloc((void**)&ctx->tables, 4 * 64);
+    if (e == hipSuccess) {
+        // table 0: the 64 -> 16 class map; table f (1..3): code -> code >> 2 for
+        // the codes whose (u, v) part is f, every other code to the discard bin
+        uint8_t host[4 * 64];
+        for (int c = 0; c < 64; ++c) {
+            host[c] = kTable.t[c];
+            for (int f = 1; f < 4; ++f) host[64 * f + c] = (c & 3) == f ? (uint8_t)(c >> 2) : (uint8_t)kNumClasses;
+        }
+        e = hipMemcpy(ctx->tables, host, sizeof(host), hipMemcpyHostToDevice);
+    }
+    for (int i = 0; i < 2 * kBuckets + 2 && e == hipSuccess; ++i) e = hipEventCreate(&ctx->ev[i]);
     if (e == hipSuccess) {
         size_t free_b = 0, total_b = 0;
         e = hipMemGetInfo(&free_b, &total_b);
@@ -216,9 +254,10 @@ int tc_context_destroy(tc_context ctx) {
         ctx->graphs.clear();
     }
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
-    for (int i = 0; i < 2 * kBuckets; ++i)
+    for (int i = 0; i < 2 * kBuckets + 2; ++i)
         if (ctx->ev[i]) (void)hipEventDestroy(ctx->ev[i]);
     if (ctx->acc) (void)hipFree(ctx->acc);
+    if (ctx->tables) (void)hipFree(ctx->tables);
     if (ctx->counters) (void)hipFree(ctx->counters);
     if (ctx->host_raw) (void)hipHostFree(ctx->host_raw);
     if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
@@ -236,7 +275,7 @@ int tc_build_graph(tc_context ctx, int32_t n, int64_t m, const int32_t* src, con
     tc_graph_s* g = new (std::nothrow) tc_graph_s();
     if (!g) return TC_ERR_NOMEM;
     std::lock_guard<std::mutex> lk(ctx->mu);
-    int rc = build_into(n, m, src, dst, flags, ctx->tuning.t0, ctx->tuning.t1, ctx->stream, &g->g, &g->info);
+    int rc = build_into(n, m, src, dst, flags, params_of(ctx->tuning), ctx->stream, &g->g, &g->info);
     if (rc != TC_OK) {
         delete g;
         return rc;
@@ -275,9 +314,33 @@ int tc_census(tc_context ctx, tc_graph g, uint64_t counts[16]) {
     std::lock_guard<std::mutex> lk(ctx->mu);
     if (!ctx->graphs.count(g)) return TC_ERR_ARG;
     unsigned long long raw[16];
-    int rc = run_census_locked(ctx, g->g, full_slices(g->g), raw);
+    int rc = run_full_locked(ctx, g->g, raw);
     if (rc != TC_OK) return rc;
     finalize_counts(g->g.n, raw, counts);
+    return TC_OK;
+}
+
+int tc_census64(tc_context ctx, tc_graph g, uint64_t counts[64]) {
+    if (!ctx || !g || !counts) return TC_ERR_ARG;
+    if (hipSetDevice(ctx->device) != hipSuccess) return TC_ERR_DEVICE;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    if (!ctx->graphs.count(g)) return TC_ERR_ARG;
+    uint64_t out[64] = {0};
+    typedef unsigned __int128 u128;
+    u128 sum = 0;
+    for (int f = 1; f < 4; ++f) {
+        unsigned long long raw[16];
+        int rc = run_full_locked(ctx, g->g, raw, f);
+        if (rc != TC_OK) return rc;
+        for (int b = 0; b < kNumClasses; ++b) {
+            out[f | (b << 2)] = raw[b];
+            sum += raw[b];
+        }
+    }
+    const int64_t n = g->g.n;
+    const u128 total = n >= 3 ? (u128)n * (u128)(n - 1) * (u128)(n - 2) / 6 : 0;
+    out[0] = (uint64_t)(total - sum);
+    std::memcpy(counts, out, sizeof(out));
     return TC_OK;
 }
 
@@ -309,10 +372,14 @@ int tc_census_range(tc_context ctx, tc_graph g, int32_t u_begin, int32_t u_end, 
         (void)hipFree(off_dev);
         if (e != hipSuccess) return status_from_hip(e);
         census_slices sl;
-        for (int b = 0; b < kBuckets; ++b) {
+        for (int b = 0; b < kBucketHub; ++b) {
             sl.begin[b] = bnd[2 * b];
             sl.end[b] = bnd[2 * b + 1];
         }
+        sl.begin[kBucketHub] = g->g.bucket_off[kBucketHub];
+        sl.end[kBucketHub] = g->g.bucket_off[kBucketHub + 1];
+        sl.u_lo = (uint32_t)u_begin;
+        sl.u_hi = (uint32_t)u_end;
         int rc = run_census_locked(ctx, g->g, sl, raw);
         if (rc != TC_OK) return rc;
     }
@@ -329,7 +396,7 @@ int tc_census_each(tc_context ctx, const tc_graph* graphs, int32_t count, uint64
         if (!graphs[i] || !ctx->graphs.count(graphs[i])) return TC_ERR_ARG;
     for (int32_t i = 0; i < count; ++i) {
         unsigned long long raw[16];
-        int rc = run_census_locked(ctx, graphs[i]->g, full_slices(graphs[i]->g), raw);
+        int rc = run_full_locked(ctx, graphs[i]->g, raw);
         if (rc != TC_OK) return rc;
         finalize_counts(graphs[i]->g.n, raw, counts + 16 * (size_t)i);
     }
@@ -338,7 +405,8 @@ int tc_census_each(tc_context ctx, const tc_graph* graphs, int32_t count, uint64
 
 int tc_set_tuning(tc_context ctx, const tc_tuning* t) {
     if (!ctx || !t) return TC_ERR_ARG;
-    if (t->t0 > t->t1 || t->lane_blocks == 0 || t->wave_blocks == 0 || t->group_blocks == 0 || t->batch_blocks == 0)
+    if (t->t0 > t->t1 || t->lane_blocks == 0 || t->wave_blocks == 0 || t->group_blocks == 0 || t->batch_blocks == 0 ||
+        t->hub_blocks == 0 || t->tri > 1)
         return TC_ERR_ARG;
     std::lock_guard<std::mutex> lk(ctx->mu);
     ctx->tuning = *t;
@@ -358,9 +426,11 @@ int tc_graph_rebucket(tc_context ctx, tc_graph g) {
     std::lock_guard<std::mutex> lk(ctx->mu);
     if (!ctx->graphs.count(g)) return TC_ERR_ARG;
     if (g->pending.load() > 0) return TC_ERR_BUSY;
-    if (g->g.t0 == ctx->tuning.t0 && g->g.t1 == ctx->tuning.t1) return TC_OK;
+    const bucket_params bp = params_of(ctx->tuning);
+    if (g->g.bp.t0 == bp.t0 && g->g.bp.t1 == bp.t1 && g->g.bp.t_hub == bp.t_hub && g->g.bp.tri == bp.tri)
+        return TC_OK;
     batch_forget_graph_locked(ctx, g);
-    return status_from_hip(bucket_dyads(&g->g, ctx->tuning.t0, ctx->tuning.t1, ctx->stream));
+    return status_from_hip(bucket_dyads(&g->g, bp, ctx->stream));
 }
 
 int tc_set_timing(tc_context ctx, int enable) {

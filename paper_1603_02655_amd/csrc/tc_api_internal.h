@@ -35,7 +35,9 @@ struct tc_context_s {
     unsigned long long* acc = nullptr;  // 16 accumulators (device)
     unsigned int* counters = nullptr;   // work counters (device)
     unsigned long long* host_raw = nullptr;  // pinned copy of acc
-    hipEvent_t ev[2 * tc::kBuckets] = {};
+    uint8_t* tables = nullptr;          // 4 x 64 bin indices (device): the 16-class table,
+                                        // then the labelled census's pass tables for f_uv = 1, 2, 3
+    hipEvent_t ev[2 * tc::kBuckets + 2] = {};
     bool timing = false;
     tc_kernel_stats kstats{};
     tc_tuning tuning{};
@@ -48,24 +50,35 @@ namespace tc {
 
 int status_from_hip(hipError_t e);
 void finalize_counts(int64_t n, const unsigned long long* raw, uint64_t out[16]);
-census_slices full_slices(const device_graph& g);
+census_slices full_slices(const device_graph& g, bool tri = false);
 census_config config_of(const tc_tuning& t);
 void fill_info(const tc_graph_s* g, tc_graph_info* info);
-int run_census_locked(tc_context_s* ctx, const device_graph& g, const census_slices& sl, unsigned long long raw[16]);
+// Runs the bucket kernels over `sl` with table `table` (0: 16 classes; 1..3:
+// labelled census pass for f_uv = table) and copies the 16 raw sums to host.
+// With `tri` the slices index the forward-list edge records.
+int run_census_locked(tc_context_s* ctx, const device_graph& g, const census_slices& sl, unsigned long long raw[16],
+                      int table = 0, bool tri = false);
+// The whole census of g: through the forward lists when the tuning asks for
+// them and g has them, else through the dyad records.
+int run_full_locked(tc_context_s* ctx, const device_graph& g, unsigned long long raw[16], int table = 0);
 // Builds a device graph from host (or, with TC_BUILD_DEVICE_PTRS, device) arcs
 // on `stream`; returns a TC_* status and fills the build part of *info.
-int build_into(int32_t n, int64_t m, const int32_t* src, const int32_t* dst, uint32_t flags, uint32_t t0, uint32_t t1,
+int build_into(int32_t n, int64_t m, const int32_t* src, const int32_t* dst, uint32_t flags, const bucket_params& bp,
                hipStream_t stream, device_graph* out, tc_graph_info* info);
+bucket_params params_of(const tc_tuning& t);
 
 inline tc_tuning default_tuning(int cu_count) {
     tc_tuning t;
     int cu = cu_count > 0 ? cu_count : 256;
     t.t0 = 64;      // lane mode for k < 64
     t.t1 = 4096;    // wave mode for 64 <= k < 4096, group mode above
+    t.t_hub = 64;   // records with a row of length >= 64: hub mode
     t.lane_blocks = (uint32_t)cu * 8;
     t.wave_blocks = (uint32_t)cu * 10;
     t.group_blocks = (uint32_t)cu * 2;
     t.batch_blocks = (uint32_t)cu * 3;
+    t.hub_blocks = (uint32_t)cu * 3;
+    t.tri = 1;      // whole-graph census through the triangles of the forward lists
     return t;
 }
 

@@ -56,9 +56,10 @@ void batch_forget_graph_locked(tc_context_s* ctx, tc_graph g) {
     }
 }
 
-// Work items of one graph: group-mode dyads first (largest), then wave-mode
-// chunks, then lane-mode chunks.
+// Work items of one graph: hub tasks and group-mode dyads first (largest),
+// then wave-mode chunks, then lane-mode chunks.
 void append_items(const device_graph& g, uint32_t gi, std::vector<work_item>& out) {
+    for (uint32_t t = 0; t < g.n_hub_tasks; ++t) out.push_back(work_item{gi, kItemHub, t, t + 1});
     for (uint64_t d = g.bucket_off[2]; d < g.bucket_off[3]; ++d)
         out.push_back(work_item{gi, kItemGroup, (uint32_t)d, (uint32_t)d + 1});
     for (uint64_t d = g.bucket_off[1]; d < g.bucket_off[2]; d += kBatchWavePerItem)
@@ -127,7 +128,7 @@ extern "C" int tc_census_batch(tc_context ctx, const tc_graph* graphs, int32_t c
         std::vector<graph_desc> descs(count);
         for (int32_t i = 0; i < count; ++i) {
             const device_graph& g = graphs[i]->g;
-            descs[i] = graph_desc{g.dyads, g.nbr, g.tpre, (uint64_t)g.n};
+            descs[i] = graph_desc{g.dyads, g.nbr, g.tpre, (uint64_t)g.n, g.hub_tasks, 0};
             append_items(g, (uint32_t)i, items);
         }
         e = ensure_capacity(p, (uint32_t)count, (uint32_t)items.size(), ctx->stream, ctx->tuning.batch_blocks);

@@ -260,39 +260,66 @@ __global__ __launch_bounds__(kT) void k_deg_stats(const int64_t* __restrict__ ro
     }
 }
 
-// ---- canonical dyads: bucket key |N(u)|+|N(v)|-2, stable partition --------
-__device__ inline int dyad_bucket(const uint32_t* nbr, const uint32_t* owner, const int64_t* row_ptr,
-                                  uint64_t e, uint64_t U, uint32_t t0, uint32_t t1, uint64_t* cost) {
+// ---- dyads: buckets, stable partition, hub tasks --------------------------
+// Every connected pair is emitted once.  A pair whose larger degree is at
+// least t_hub is a hub dyad, emitted from its anchor's row (the endpoint of
+// larger degree, ties to the larger id), so the hub bucket is anchor-major;
+// any other pair is emitted from the row of its smaller id (u-major) into the
+// lane / wave / group bucket by k = |N(u)| + |N(v)| - 2.
+// Bucket of entry e of an adjacency view.  Dyad view (tri = 0): the dyad is
+// emitted once, from its first vertex, or from its anchor in the hub bucket.
+// Forward view (tri = 1): every entry is one oriented edge and is emitted,
+// unless one of the two forward lists is empty (no shared vertex possible).
+// Hub: the longer of the two rows reaches t_hub; the anchor is the endpoint
+// with the longer row (ties to the larger id).
+__device__ inline int rec_bucket(const uint32_t* nbr, const uint32_t* owner, const int64_t* row_ptr,
+                                 uint64_t e, uint64_t U, const bucket_params& bp, int tri, uint64_t* cost,
+                                 uint64_t* stream, uint32_t* anchor) {
     if (e >= U) return kBuckets;
-    uint32_t o = owner[e], w = nbr[e] >> 2;
-    if (!(o < w)) return kBuckets;
-    uint64_t du = (uint64_t)(row_ptr[o + 1] - row_ptr[o]), dv = (uint64_t)(row_ptr[w + 1] - row_ptr[w]);
-    *cost = du + dv;
-    uint64_t k = du + dv - 2;
-    return k < t0 ? 0 : (k < t1 ? 1 : 2);
+    const uint32_t o = owner[e], w = nbr[e] >> 2;
+    const uint64_t d_o = (uint64_t)(row_ptr[o + 1] - row_ptr[o]), d_w = (uint64_t)(row_ptr[w + 1] - row_ptr[w]);
+    if (tri && (d_o == 0 || d_w == 0)) return kBuckets;
+    *cost = d_o + d_w;
+    if ((d_o > d_w ? d_o : d_w) >= bp.t_hub) {
+        const bool o_anchor = d_o > d_w || (d_o == d_w && o > w);
+        if (!tri && !o_anchor) return kBuckets;
+        *stream = o_anchor ? d_w : d_o;
+        *anchor = o_anchor ? o : w;
+        return kBucketHub;
+    }
+    if (!tri && !(o < w)) return kBuckets;
+    const uint64_t k = tri ? d_o + d_w : d_o + d_w - 2;
+    return k < bp.t0 ? 0 : (k < bp.t1 ? 1 : 2);
 }
 
 __global__ __launch_bounds__(kT) void k_dyad_count(const uint32_t* __restrict__ nbr, const uint32_t* __restrict__ owner,
-                                                    const int64_t* __restrict__ row_ptr, uint64_t U, uint32_t t0,
-                                                    uint32_t t1, uint64_t* __restrict__ counts, uint32_t nblocks,
+                                                    const int64_t* __restrict__ row_ptr, uint64_t U, bucket_params bp,
+                                                    int tri, uint64_t* __restrict__ counts, uint32_t nblocks,
+                                                    unsigned int* __restrict__ hubcnt,
                                                     unsigned long long* __restrict__ counters) {
     __shared__ uint32_t c[kBuckets];
     __shared__ unsigned long long cost_sh[kBuckets];
+    __shared__ unsigned long long stream_sh;
     __shared__ uint32_t mutual_sh;
     if (threadIdx.x < kBuckets) { c[threadIdx.x] = 0; cost_sh[threadIdx.x] = 0; }
-    if (threadIdx.x == 0) mutual_sh = 0;
+    if (threadIdx.x == 0) { mutual_sh = 0; stream_sh = 0; }
     __syncthreads();
     uint64_t base = (uint64_t)blockIdx.x * kTile;
-    uint32_t my[kBuckets] = {0, 0, 0}, mut = 0;
-    unsigned long long mycost[kBuckets] = {0, 0, 0};
+    uint32_t my[kBuckets] = {0, 0, 0, 0}, mut = 0;
+    unsigned long long mycost[kBuckets] = {0, 0, 0, 0}, mystream = 0;
     for (int k = 0; k < kI; ++k) {
         uint64_t e = base + (uint64_t)k * kT + threadIdx.x;
-        uint64_t cost = 0;
-        int b = dyad_bucket(nbr, owner, row_ptr, e, U, t0, t1, &cost);
+        uint64_t cost = 0, stream = 0;
+        uint32_t anchor = 0;
+        int b = rec_bucket(nbr, owner, row_ptr, e, U, bp, tri, &cost, &stream, &anchor);
         if (b < kBuckets) {
             my[b]++;
             mycost[b] += cost;
             mut += ((nbr[e] & 3u) == 3u) ? 1u : 0u;
+            if (b == kBucketHub) {
+                mystream += stream;
+                atomicAdd(&hubcnt[anchor], 1u);
+            }
         }
     }
     for (int b = 0; b < kBuckets; ++b) {
@@ -300,12 +327,14 @@ __global__ __launch_bounds__(kT) void k_dyad_count(const uint32_t* __restrict__ 
         if (mycost[b]) atomicAdd(&cost_sh[b], mycost[b]);
     }
     if (mut) atomicAdd(&mutual_sh, mut);
+    if (mystream) atomicAdd(&stream_sh, mystream);
     __syncthreads();
     if (threadIdx.x < kBuckets) {
         counts[(uint64_t)threadIdx.x * nblocks + blockIdx.x] = c[threadIdx.x];
         if (cost_sh[threadIdx.x]) atomicAdd(&counters[8 + threadIdx.x], cost_sh[threadIdx.x]);
     }
     if (threadIdx.x == 0 && mutual_sh) atomicAdd(&counters[5], (unsigned long long)mutual_sh);
+    if (threadIdx.x == 0 && stream_sh) atomicAdd(&counters[12], stream_sh);
 }
 
 __device__ inline uint32_t find_in_row(const uint32_t* nbr, uint32_t lo, uint32_t hi, uint32_t x) {
@@ -317,15 +346,21 @@ __device__ inline uint32_t find_in_row(const uint32_t* nbr, uint32_t lo, uint32_
     return lo;
 }
 
+// Writes the records.  Lane / wave / group records keep the entry order of the
+// view (u-major for dyads) through a stable per-bucket ranking.  Hub records
+// of the dyad view come from their anchor's row and so are anchor-major in
+// entry order; hub records of the forward view may come from either endpoint
+// and are placed in their anchor's run (rec_off) through a per-anchor cursor.
 __global__ __launch_bounds__(kT) void k_dyad_scatter(const uint32_t* __restrict__ nbr, const uint32_t* __restrict__ owner,
-                                                      const int64_t* __restrict__ row_ptr, uint64_t U, uint32_t t0,
-                                                      uint32_t t1, const uint64_t* __restrict__ offsets,
-                                                      uint32_t nblocks, dyad_rec* __restrict__ out) {
+                                                      const int64_t* __restrict__ row_ptr, uint64_t U, bucket_params bp,
+                                                      int tri, const uint64_t* __restrict__ offsets, uint32_t nblocks,
+                                                      const uint64_t* __restrict__ rec_off,
+                                                      unsigned int* __restrict__ cursor, uint64_t hub_begin,
+                                                      dyad_rec* __restrict__ out) {
     __shared__ uint32_t running[kBuckets];
     __shared__ uint32_t wcnt[kT / 64][kBuckets];
     __shared__ uint64_t goff[kBuckets];
-    const int lane = __lane_id(), wid = threadIdx.x >> 6;
-    (void)lane;
+    const int wid = threadIdx.x >> 6;
     if (threadIdx.x < kBuckets) {
         running[threadIdx.x] = 0;
         goff[threadIdx.x] = offsets[(uint64_t)threadIdx.x * nblocks + blockIdx.x];
@@ -334,8 +369,9 @@ __global__ __launch_bounds__(kT) void k_dyad_scatter(const uint32_t* __restrict_
     uint64_t base = (uint64_t)blockIdx.x * kTile;
     for (int r = 0; r < kI; ++r) {
         uint64_t e = base + (uint64_t)r * kT + threadIdx.x;
-        uint64_t cost = 0;
-        int b = dyad_bucket(nbr, owner, row_ptr, e, U, t0, t1, &cost);
+        uint64_t cost = 0, stream = 0;
+        uint32_t anchor = 0;
+        int b = rec_bucket(nbr, owner, row_ptr, e, U, bp, tri, &cost, &stream, &anchor);
         uint32_t rank = 0;
         for (int q = 0; q < kBuckets; ++q) {
             uint64_t mask = __ballot(b == q);
@@ -346,17 +382,34 @@ __global__ __launch_bounds__(kT) void k_dyad_scatter(const uint32_t* __restrict_
         if (b < kBuckets) {
             uint32_t before = running[b];
             for (int w = 0; w < wid; ++w) before += wcnt[w][b];
-            uint32_t o = owner[e], ent = nbr[e], v = ent >> 2;
+            const uint32_t o = owner[e], x = nbr[e] >> 2;
+            const uint32_t u = o < x ? o : x, v = o < x ? x : o;
             dyad_rec rec;
-            rec.bu = (uint32_t)row_ptr[o];
-            rec.eu = (uint32_t)row_ptr[o + 1];
+            rec.bu = (uint32_t)row_ptr[u];
+            rec.eu = (uint32_t)row_ptr[u + 1];
             rec.bv = (uint32_t)row_ptr[v];
             rec.ev = (uint32_t)row_ptr[v + 1];
-            rec.iv = (uint32_t)e;
-            rec.iu = find_in_row(nbr, rec.bv, rec.ev, o);
-            rec.u = o;
-            rec.vf = ent;
-            out[goff[b] + before + rank] = rec;
+            rec.u = u;
+            if (tri) {
+                const uint32_t fo = nbr[e] & 3u;
+                const uint32_t fuv = o == u ? fo : ((fo & 1u) << 1) | (fo >> 1);
+                rec.iv = 0;
+                rec.iu = 0;
+                rec.vf = (v << 2) | fuv;
+            } else {
+                if (o == u) {
+                    rec.iv = (uint32_t)e;
+                    rec.iu = find_in_row(nbr, rec.bv, rec.ev, u);
+                } else {
+                    rec.iu = (uint32_t)e;
+                    rec.iv = find_in_row(nbr, rec.bu, rec.eu, v);
+                }
+                rec.vf = nbr[rec.iv];   // (v << 2) | f_uv
+            }
+            if (tri && b == kBucketHub)
+                out[hub_begin + rec_off[anchor] + atomicAdd(&cursor[anchor], 1u)] = rec;
+            else
+                out[goff[b] + before + rank] = rec;
         }
         __syncthreads();
         if (threadIdx.x < kBuckets) {
@@ -366,6 +419,78 @@ __global__ __launch_bounds__(kT) void k_dyad_scatter(const uint32_t* __restrict_
         }
         __syncthreads();
     }
+}
+
+// Forward lists: flag the entries whose vertex follows the row's owner in
+// degree order, compact them (order kept, so rows stay sorted by id), and read
+// each row's start off the scanned flags.
+__global__ __launch_bounds__(kT) void k_fwd_flag(const uint32_t* __restrict__ nbr, const uint32_t* __restrict__ owner,
+                                                  const int64_t* __restrict__ row_ptr, uint64_t U,
+                                                  uint64_t* __restrict__ flag) {
+    const uint64_t e = (uint64_t)blockIdx.x * kT + threadIdx.x;
+    if (e >= U) return;
+    const uint32_t o = owner[e], w = nbr[e] >> 2;
+    const int64_t d_o = row_ptr[o + 1] - row_ptr[o], d_w = row_ptr[w + 1] - row_ptr[w];
+    flag[e] = (d_w > d_o || (d_w == d_o && w > o)) ? 1u : 0u;
+}
+
+__global__ __launch_bounds__(kT) void k_fwd_emit(const uint32_t* __restrict__ nbr, const uint32_t* __restrict__ owner,
+                                                  uint64_t U, const uint64_t* __restrict__ pos,
+                                                  uint32_t* __restrict__ fwd, uint32_t* __restrict__ fwd_owner) {
+    const uint64_t e = (uint64_t)blockIdx.x * kT + threadIdx.x;
+    if (e >= U || pos[e + 1] == pos[e]) return;
+    fwd[pos[e]] = nbr[e];
+    fwd_owner[pos[e]] = owner[e];
+}
+
+__global__ __launch_bounds__(kT) void k_fwd_ptr(const int64_t* __restrict__ row_ptr, int32_t n,
+                                                 const uint64_t* __restrict__ pos, int64_t* __restrict__ fwd_ptr) {
+    const int64_t x = (int64_t)blockIdx.x * kT + threadIdx.x;
+    if (x <= n) fwd_ptr[x] = (int64_t)pos[row_ptr[x]];
+}
+
+// Hub tasks: the hub records of anchor row h are contiguous, starting at
+// row_off[h] inside the hub bucket; they are cut into runs of kHubChunk.
+// Tasks of anchors whose row is longer than `big_row` are placed first (they
+// are the longest), the others after them: `big` selects which of the two
+// classes this pass counts.
+__global__ __launch_bounds__(kT) void k_hub_ntasks(const unsigned int* __restrict__ hubcnt, int32_t n,
+                                                    const int64_t* __restrict__ row_ptr, uint64_t* __restrict__ ntask,
+                                                    uint64_t big_row, int big, unsigned long long* __restrict__ counters) {
+    int32_t h = (int32_t)(blockIdx.x * kT + threadIdx.x);
+    unsigned long long staged = 0;
+    if (h < n) {
+        const uint64_t d = (uint64_t)(row_ptr[h + 1] - row_ptr[h]);
+        uint64_t t = (hubcnt[h] + kHubChunk - 1) / kHubChunk;
+        if ((d > big_row) != (big != 0)) t = 0;
+        ntask[h] = t;
+        staged = t * (unsigned long long)d;
+    }
+    for (int off = 32; off > 0; off >>= 1) staged += __shfl_xor(staged, off, 64);
+    if (counters && __lane_id() == 0 && staged) atomicAdd(&counters[13], staged);
+}
+
+__global__ __launch_bounds__(kT) void k_hub_emit(const unsigned int* __restrict__ hubcnt, int32_t n,
+                                                  const int64_t* __restrict__ row_ptr, const uint64_t* __restrict__ rec_off,
+                                                  const uint64_t* __restrict__ task_off, uint64_t task_base, uint64_t big_row,
+                                                  int big, uint64_t hub_begin, hub_task* __restrict__ tasks) {
+    int32_t h = (int32_t)(blockIdx.x * kT + threadIdx.x);
+    if (h >= n) return;
+    if (((uint64_t)(row_ptr[h + 1] - row_ptr[h]) > big_row) != (big != 0)) return;
+    const uint64_t c = hubcnt[h], base = hub_begin + rec_off[h], t0 = task_base + task_off[h];
+    for (uint64_t j = 0; j * kHubChunk < c; ++j) {
+        hub_task t;
+        t.begin = (uint32_t)(base + j * kHubChunk);
+        t.end = (uint32_t)(base + (c < (j + 1) * kHubChunk ? c : (j + 1) * kHubChunk));
+        t.anchor = (uint32_t)h;
+        t.pad = 0;
+        tasks[t0 + j] = t;
+    }
+}
+
+__global__ void k_u32_to_u64(const unsigned int* __restrict__ a, uint64_t* __restrict__ b, uint64_t n) {
+    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = a[i];
 }
 
 __global__ void k_fill_u64(uint64_t* p, uint64_t n, uint64_t v) {
@@ -429,7 +554,7 @@ static uint32_t bit_width_u32(uint32_t x) {
 #define TRY(x) do { hipError_t _e = (x); if (_e != hipSuccess) { err = _e; goto done; } } while (0)
 
 build_status build_graph_device(int32_t n, int64_t m, const int32_t* src_dev, const int32_t* dst_dev,
-                                uint32_t t0, uint32_t t1, hipStream_t s, device_graph* g) {
+                                const bucket_params& bp, hipStream_t s, device_graph* g) {
     build_status st{};
     hipError_t err = hipSuccess;
     uint64_t *keys = nullptr, *tmp = nullptr, *heads = nullptr, *uidx = nullptr, *degs = nullptr;
@@ -501,7 +626,7 @@ build_status build_graph_device(int32_t n, int64_t m, const int32_t* src_dev, co
         st.sum_d2 = hc[3];
         st.max_degree = (int64_t)hc[4];
     }
-    TRY(bucket_dyads(g, t0, t1, s));
+    TRY(bucket_dyads(g, bp, s));
     st.ok = true;
 done:
     if (keys) (void)hipFreeAsync(keys, s);
@@ -518,19 +643,35 @@ done:
     return st;
 }
 
-hipError_t bucket_dyads(device_graph* g, uint32_t t0, uint32_t t1, hipStream_t s) {
+// Buckets the entries of one adjacency view (nbr / owner / row_ptr over U
+// entries and n rows) into `out`: records, hub tasks and the per-bucket sums.
+static hipError_t bucket_records(const uint32_t* nbr, const uint32_t* owner, const int64_t* row_ptr, uint64_t U,
+                                 int32_t n, int tri, const bucket_params& bp, hipStream_t s, rec_set* out,
+                                 uint64_t* mutual) {
     hipError_t err = hipSuccess;
     uint64_t* counts = nullptr;
     unsigned long long* counters = nullptr;
+    unsigned int *hubcnt = nullptr, *cursor = nullptr;
+    uint64_t *rec_off = nullptr, *task_off = nullptr, *tmp64 = nullptr;
     unsigned long long hc[kCounters] = {0};
-    uint64_t off_host[kBuckets + 1] = {0, 0, 0, 0};
-    uint64_t U = g->U;
-    uint32_t nb = blocks_for(U ? U : 1);
-    if (g->dyads) { (void)hipFree(g->dyads); g->dyads = nullptr; }
+    uint64_t off_host[kBuckets + 1] = {0, 0, 0, 0, 0};
+    uint64_t ntasks = 0, total = 0;
+    const uint32_t nb = blocks_for(U ? U : 1);
+    if (out->recs) (void)hipFree(out->recs);
+    if (out->tasks) (void)hipFree(out->tasks);
+    *out = rec_set{};
     TRY(hipMallocAsync((void**)&counters, sizeof(unsigned long long) * kCounters, s));
     TRY(fill_u64((uint64_t*)counters, kCounters, 0, s));
     TRY(hipMallocAsync((void**)&counts, sizeof(uint64_t) * ((size_t)kBuckets * nb + 1), s));
-    hipLaunchKernelGGL(k_dyad_count, dim3(nb), dim3(kT), 0, s, g->nbr, g->owner, g->row_ptr, U, t0, t1, counts, nb,
+    TRY(hipMallocAsync((void**)&hubcnt, sizeof(unsigned int) * ((size_t)n + 2), s));
+    TRY(fill_u64((uint64_t*)hubcnt, ((uint64_t)n + 2) / 2, 0, s));
+    TRY(hipMallocAsync((void**)&rec_off, sizeof(uint64_t) * ((size_t)n + 1), s));
+    TRY(hipMallocAsync((void**)&tmp64, sizeof(uint64_t) * ((size_t)n + 1), s));
+    if (tri) {
+        TRY(hipMallocAsync((void**)&cursor, sizeof(unsigned int) * ((size_t)n + 2), s));
+        TRY(fill_u64((uint64_t*)cursor, ((uint64_t)n + 2) / 2, 0, s));
+    }
+    hipLaunchKernelGGL(k_dyad_count, dim3(nb), dim3(kT), 0, s, nbr, owner, row_ptr, U, bp, tri, counts, nb, hubcnt,
                        counters);
     TRY(hipGetLastError());
     TRY(scan_exclusive_u64(counts, counts, (uint64_t)kBuckets * nb, counts + (uint64_t)kBuckets * nb, s));
@@ -539,44 +680,167 @@ hipError_t bucket_dyads(device_graph* g, uint32_t t0, uint32_t t1, hipStream_t s
         TRY(hipMemcpyAsync(&off_host[b], counts + (uint64_t)b * nb, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
     TRY(hipMemcpyAsync(&off_host[kBuckets], counts + (uint64_t)kBuckets * nb, sizeof(uint64_t),
                        hipMemcpyDeviceToHost, s));
-    TRY(hipMemcpyAsync(hc, counters, sizeof(hc), hipMemcpyDeviceToHost, s));
-    TRY(hipStreamSynchronize(s));
-    g->p = off_host[kBuckets];
-    for (int b = 0; b <= kBuckets; ++b) g->bucket_off[b] = off_host[b];
-    for (int b = 0; b < kBuckets; ++b) g->bucket_cost[b] = hc[8 + b];
-    g->mutual = hc[5];
-    g->t0 = t0;
-    g->t1 = t1;
-    TRY(hipMalloc((void**)&g->dyads, sizeof(dyad_rec) * (g->p ? g->p : 1)));
-    if (g->p > 0) {
-        hipLaunchKernelGGL(k_dyad_scatter, dim3(nb), dim3(kT), 0, s, g->nbr, g->owner, g->row_ptr, U, t0, t1,
-                           (const uint64_t*)counts, nb, g->dyads);
+    // per anchor: offset of its run of hub records
+    if (n > 0) {
+        hipLaunchKernelGGL(k_u32_to_u64, dim3(grid1((uint64_t)n)), dim3(kT), 0, s, hubcnt, tmp64, (uint64_t)n);
         TRY(hipGetLastError());
+        TRY(scan_exclusive_u64(tmp64, rec_off, (uint64_t)n, rec_off + n, s));
     }
     TRY(hipStreamSynchronize(s));
+    total = off_host[kBuckets];
+    for (int b = 0; b <= kBuckets; ++b) out->off[b] = off_host[b];
+    TRY(hipMalloc((void**)&out->recs, sizeof(dyad_rec) * (total ? total : 1)));
+    if (total > 0) {
+        hipLaunchKernelGGL(k_dyad_scatter, dim3(nb), dim3(kT), 0, s, nbr, owner, row_ptr, U, bp, tri,
+                           (const uint64_t*)counts, nb, (const uint64_t*)rec_off, cursor, out->off[kBucketHub],
+                           out->recs);
+        TRY(hipGetLastError());
+    }
+    // hub tasks: runs of at most kHubChunk records per anchor
+    if (out->off[kBucketHub + 1] > out->off[kBucketHub] && n > 0) {
+        TRY(hipMallocAsync((void**)&task_off, sizeof(uint64_t) * ((size_t)n + 1), s));
+        // two passes: anchors with rows of several LDS tiles first, then the rest
+        uint64_t part[2] = {0, 0};
+        for (int big = 1; big >= 0; --big) {
+            hipLaunchKernelGGL(k_hub_ntasks, dim3(grid1((uint64_t)n)), dim3(kT), 0, s, hubcnt, n, row_ptr, tmp64,
+                               (uint64_t)kHubTileEntries, big, counters);
+            TRY(hipGetLastError());
+            TRY(scan_exclusive_u64(tmp64, task_off, (uint64_t)n, task_off + n, s));
+            TRY(hipMemcpyAsync(&part[big], task_off + n, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+            TRY(hipStreamSynchronize(s));
+        }
+        ntasks = part[1] + part[0];
+        TRY(hipMalloc((void**)&out->tasks, sizeof(hub_task) * (ntasks ? ntasks : 1)));
+        for (int big = 1; big >= 0; --big) {
+            hipLaunchKernelGGL(k_hub_ntasks, dim3(grid1((uint64_t)n)), dim3(kT), 0, s, hubcnt, n, row_ptr, tmp64,
+                               (uint64_t)kHubTileEntries, big, (unsigned long long*)nullptr);
+            TRY(hipGetLastError());
+            TRY(scan_exclusive_u64(tmp64, task_off, (uint64_t)n, task_off + n, s));
+            hipLaunchKernelGGL(k_hub_emit, dim3(grid1((uint64_t)n)), dim3(kT), 0, s, hubcnt, n, row_ptr, rec_off,
+                               task_off, big ? (uint64_t)0 : part[1], (uint64_t)kHubTileEntries, big,
+                               out->off[kBucketHub], out->tasks);
+            TRY(hipGetLastError());
+        }
+        out->n_tasks = (uint32_t)ntasks;
+    }
+    TRY(hipMemcpyAsync(hc, counters, sizeof(hc), hipMemcpyDeviceToHost, s));
+    TRY(hipStreamSynchronize(s));
+    for (int b = 0; b < kBuckets; ++b) out->cost[b] = hc[8 + b];
+    if (mutual) *mutual = hc[5];
+    out->stream = hc[12];
+    out->staged = hc[13];
 done:
     if (counts) (void)hipFreeAsync(counts, s);
     if (counters) (void)hipFreeAsync(counters, s);
+    if (hubcnt) (void)hipFreeAsync(hubcnt, s);
+    if (cursor) (void)hipFreeAsync(cursor, s);
+    if (rec_off) (void)hipFreeAsync(rec_off, s);
+    if (task_off) (void)hipFreeAsync(task_off, s);
+    if (tmp64) (void)hipFreeAsync(tmp64, s);
     (void)hipStreamSynchronize(s);
+    return err;
+}
+
+static void free_forward(forward_lists* t) {
+    if (t->fwd) (void)hipFree(t->fwd);
+    if (t->fwd_owner) (void)hipFree(t->fwd_owner);
+    if (t->fwd_ptr) (void)hipFree(t->fwd_ptr);
+    if (t->edges.recs) (void)hipFree(t->edges.recs);
+    if (t->edges.tasks) (void)hipFree(t->edges.tasks);
+    *t = forward_lists{};
+}
+
+// Forward lists of g (degree order), built once per graph.
+static hipError_t build_forward(device_graph* g, hipStream_t s) {
+    hipError_t err = hipSuccess;
+    uint64_t* pos = nullptr;
+    const uint64_t U = g->U;
+    const int32_t n = g->n;
+    forward_lists& t = g->tri;
+    TRY(hipMalloc((void**)&t.fwd_ptr, sizeof(int64_t) * ((size_t)n + 1)));
+    TRY(hipMallocAsync((void**)&pos, sizeof(uint64_t) * (U + 1), s));
+    if (U > 0) {
+        hipLaunchKernelGGL(k_fwd_flag, dim3(grid1(U)), dim3(kT), 0, s, g->nbr, g->owner, g->row_ptr, U, pos);
+        TRY(hipGetLastError());
+    }
+    TRY(scan_exclusive_u64(pos, pos, U, pos + U, s));
+    TRY(hipMemcpyAsync(&t.entries, pos + U, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+    TRY(hipStreamSynchronize(s));
+    TRY(hipMalloc((void**)&t.fwd, sizeof(uint32_t) * (t.entries ? t.entries : 1)));
+    TRY(hipMalloc((void**)&t.fwd_owner, sizeof(uint32_t) * (t.entries ? t.entries : 1)));
+    if (U > 0) {
+        hipLaunchKernelGGL(k_fwd_emit, dim3(grid1(U)), dim3(kT), 0, s, g->nbr, g->owner, U, (const uint64_t*)pos,
+                           t.fwd, t.fwd_owner);
+        TRY(hipGetLastError());
+    }
+    hipLaunchKernelGGL(k_fwd_ptr, dim3(grid1((uint64_t)n + 1)), dim3(kT), 0, s, g->row_ptr, n,
+                       (const uint64_t*)pos, t.fwd_ptr);
+    TRY(hipGetLastError());
+done:
+    if (pos) (void)hipFreeAsync(pos, s);
+    (void)hipStreamSynchronize(s);
+    return err;
+}
+
+hipError_t bucket_dyads(device_graph* g, const bucket_params& bp, hipStream_t s) {
+    rec_set d;
+    d.recs = g->dyads;
+    d.tasks = g->hub_tasks;
+    g->dyads = nullptr;
+    g->hub_tasks = nullptr;
+    g->n_hub_tasks = 0;
+    uint64_t mutual = 0;
+    hipError_t err = bucket_records(g->nbr, g->owner, g->row_ptr, g->U, g->n, 0, bp, s, &d, &mutual);
+    g->dyads = d.recs;
+    g->hub_tasks = d.tasks;
+    if (err != hipSuccess) return err;
+    g->n_hub_tasks = d.n_tasks;
+    g->p = d.off[kBuckets];
+    for (int b = 0; b <= kBuckets; ++b) g->bucket_off[b] = d.off[b];
+    for (int b = 0; b < kBuckets; ++b) g->bucket_cost[b] = d.cost[b];
+    g->mutual = mutual;
+    g->hub_stream = d.stream;
+    g->hub_staged = d.staged;
+    g->bp = bp;
+    if (!bp.tri) {
+        free_forward(&g->tri);
+        return hipSuccess;
+    }
+    if (!g->tri.fwd_ptr) {
+        err = build_forward(g, s);
+        if (err != hipSuccess) {
+            free_forward(&g->tri);
+            return err;
+        }
+    }
+    forward_lists& t = g->tri;
+    err = bucket_records(t.fwd, t.fwd_owner, t.fwd_ptr, t.entries, g->n, 1, bp, s, &t.edges, nullptr);
+    if (err != hipSuccess) free_forward(&g->tri);
     return err;
 }
 
 #undef TRY
 
 void free_device_graph(device_graph* g) {
+    free_forward(&g->tri);
     if (g->row_ptr) (void)hipFree(g->row_ptr);
     if (g->nbr) (void)hipFree(g->nbr);
     if (g->owner) (void)hipFree(g->owner);
     if (g->tpre) (void)hipFree(g->tpre);
     if (g->dyads) (void)hipFree(g->dyads);
+    if (g->hub_tasks) (void)hipFree(g->hub_tasks);
     int32_t n = g->n;
     *g = device_graph{};
     g->n = n;
 }
 
 uint64_t device_graph_bytes(const device_graph& g) {
-    return sizeof(int64_t) * ((uint64_t)g.n + 1) + (sizeof(uint32_t) * 2 + sizeof(uint64_t)) * g.U +
-           sizeof(uint64_t) + sizeof(dyad_rec) * g.p;
+    uint64_t b = sizeof(int64_t) * ((uint64_t)g.n + 1) + (sizeof(uint32_t) * 2 + sizeof(uint64_t)) * g.U +
+                 sizeof(uint64_t) + sizeof(dyad_rec) * g.p + sizeof(hub_task) * (uint64_t)g.n_hub_tasks;
+    if (g.tri.fwd_ptr)
+        b += sizeof(int64_t) * ((uint64_t)g.n + 1) + sizeof(uint32_t) * 2 * g.tri.entries +
+             sizeof(dyad_rec) * g.tri.edges.off[kBuckets] + sizeof(hub_task) * (uint64_t)g.tri.edges.n_tasks;
+    return b;
 }
 
 }  // namespace tc

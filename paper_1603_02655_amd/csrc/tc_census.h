@@ -8,12 +8,15 @@ struct census_config {
     uint32_t lane_blocks = 2048;    // grid cap of the lane-per-dyad kernel
     uint32_t wave_blocks = 8192;    // resident one-wave workgroups of the wave kernel
     uint32_t group_blocks = 1024;   // resident workgroups of the group kernel
+    uint32_t hub_blocks = 1024;     // resident workgroups of the hub kernel
 };
 
-// Per-bucket dyad slices [begin, end) into g.dyads.
+// Per-bucket dyad slices [begin, end) into g.dyads (merge buckets); the hub
+// bucket always runs all its tasks, restricted to dyads with u in [u_lo, u_hi).
 struct census_slices {
     uint64_t begin[kBuckets];
     uint64_t end[kBuckets];
+    uint32_t u_lo = 0, u_hi = 0xffffffffu;
 };
 
 // ---- batched launch over many graphs ----
@@ -22,10 +25,13 @@ struct graph_desc {
     const uint32_t* nbr;
     const uint64_t* tpre;
     uint64_t n;
+    const hub_task* hub_tasks;
+    uint64_t pad;
 };
-enum : uint32_t { kItemLane = 0, kItemWave = 1, kItemGroup = 2 };
+enum : uint32_t { kItemLane = 0, kItemWave = 1, kItemGroup = 2, kItemHub = 3 };
 struct work_item {
-    uint32_t graph, kind, begin, end;   // dyads [begin, end) of graph `graph`'s record array
+    uint32_t graph, kind, begin, end;   // dyads [begin, end) of graph `graph`'s record array;
+                                        // hub items: hub tasks [begin, end) of the graph
 };
 constexpr uint32_t kBatchLanePerItem = 256;   // one dyad per thread of a 256-thread workgroup
 constexpr uint32_t kBatchWavePerItem = 16;    // four wavefronts, four dyads each
@@ -36,11 +42,16 @@ hipError_t batch_launch(const graph_desc* descs, const work_item* items, const u
                         unsigned long long* accs, uint64_t acc_words, unsigned int* counters, uint32_t grid,
                         hipStream_t s);
 
+// Copies the 16-class table into the constant table the batch kernel reads.
 hipError_t census_upload_table();
-// Zeroes acc (16 x u64) and counters (kBuckets x u32), then runs the three
-// bucket kernels over the given slices.  ev, when not null, holds 2*kBuckets
-// events recorded around each bucket's launch.
-hipError_t census_launch(const device_graph& g, const census_slices& sl, unsigned long long* acc,
-                         unsigned int* counters, const census_config& cfg, hipStream_t s, hipEvent_t* ev);
+// Zeroes acc (16 x u64) and counters (kBuckets x u32), then runs the bucket
+// kernels over the given slices with `table` (64 bytes of device memory: the
+// bin of every code, kNumClasses for codes that are not counted).  With `tri`
+// the slices index the forward-list edge records (g.tri.edges) and a totals
+// pass over every dyad record runs first.  ev, when not null, holds
+// 2*kBuckets + 2 events: around each bucket's launch, then around the totals.
+hipError_t census_launch(const device_graph& g, const census_slices& sl, bool tri, const uint8_t* table,
+                         unsigned long long* acc, unsigned int* counters, const census_config& cfg, hipStream_t s,
+                         hipEvent_t* ev);
 
 }  // namespace tc

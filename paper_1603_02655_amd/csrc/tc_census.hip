@@ -23,6 +23,12 @@
 // Counts accumulate in 64-bit LDS bins (private per lane in the lane mode, per
 // wavefront elsewhere); each workgroup adds its 16 sums to the graph's
 // accumulators with one 64-bit global atomic per class when it finishes.
+//
+// The class of every code comes from a 64-entry table staged in LDS.  The
+// single-graph kernels take the table as an argument: the 16-class table, or
+// for the labelled (64-class) census one of three pass tables that send the
+// codes whose (u, v) part is f to bin (code >> 2) and every other code to the
+// discard bin kDiscard, which is never flushed.
 #include "tc_census.h"
 
 namespace tc {
@@ -31,14 +37,17 @@ namespace {
 
 __constant__ uint8_t c_table[64];
 
+constexpr int kBins = kNumClasses + 1;     // 16 classes and the discard bin
+constexpr uint32_t kDiscard = kNumClasses;
+
 // ---- class histograms in LDS ------------------------------------------------
-// lane_bins: one private 16-bin row per lane (no contention; used where every
-// lane works on its own dyad).  wave_bins: 16 bins per wavefront updated with
+// lane_bins: one private row of bins per lane (no contention; used where every
+// lane works on its own dyad).  wave_bins: one row per wavefront updated with
 // LDS atomics (used where a group shares a dyad and only shared neighbours and
 // one lane's per-dyad totals are added).
 template <int B>
 struct lane_bins {
-    static constexpr int kWords = kNumClasses * B;
+    static constexpr int kWords = kBins * B;
     unsigned long long* bins;
     __device__ inline void add(uint32_t cls, unsigned long long x) {
         atomicAdd(&bins[cls * B + threadIdx.x], x);
@@ -60,10 +69,10 @@ struct lane_bins {
 
 template <int B>
 struct wave_bins {
-    static constexpr int kWords = kNumClasses * (B / 64);
+    static constexpr int kWords = kBins * (B / 64);
     unsigned long long* bins;
     __device__ inline void add(uint32_t cls, unsigned long long x) {
-        atomicAdd(&bins[(threadIdx.x >> 6) * kNumClasses + cls], x);
+        atomicAdd(&bins[(threadIdx.x >> 6) * kBins + cls], x);
     }
     __device__ inline void clear() {
         for (int i = threadIdx.x; i < kWords; i += B) bins[i] = 0;
@@ -72,7 +81,7 @@ struct wave_bins {
         __syncthreads();
         if (threadIdx.x < kNumClasses) {
             unsigned long long s = 0;
-            for (int w = 0; w < B / 64; ++w) s += bins[w * kNumClasses + threadIdx.x];
+            for (int w = 0; w < B / 64; ++w) s += bins[w * kBins + threadIdx.x];
             if (s != 0) atomicAdd(&acc[threadIdx.x], s);
         }
     }
@@ -93,7 +102,7 @@ template <class H>
 __device__ inline void add_totals(const dyad_rec& r, const dyad_totals& t, uint64_t n, const uint8_t* T, H& h) {
     const uint32_t f = r.vf & 3u;
     const uint64_t du = r.eu - r.bu, dv = r.ev - r.bv;
-    h.add(f == 3u ? 2u : 1u, (unsigned long long)(n - du - dv));
+    h.add(T[f], (unsigned long long)(n - du - dv));
     uint64_t pa = t.pa1 - t.pa0;                       // N(u) entries w > v
     uint64_t a_tot = r.eu - r.iv - 1, a_out = pa & 0xffffffffull, a_in = pa >> 32;
     uint64_t a3 = a_out + a_in - a_tot;
@@ -112,12 +121,38 @@ __device__ inline void add_totals(const dyad_rec& r, const dyad_totals& t, uint6
 template <class H>
 __device__ inline void on_common(uint32_t w, uint32_t fa, uint32_t fb, uint32_t u, uint32_t v, uint32_t f,
                                  const uint8_t* T, H& h) {
-    h.add(f == 3u ? 2u : 1u, 1ull);                       // |S| is one smaller
+    h.add(T[f], 1ull);                                    // |S| is one smaller
     if (w > v) {                                          // counted with its full code
         h.add(T[f | (fa << 2) | (fb << 4)], 1ull);
         h.add(T[f | (fa << 2)], ~0ull);                   // not a u-only vertex
     }
     if (w > u) h.add(T[f | (fb << 4)], ~0ull);            // not a v-only vertex
+}
+
+__device__ inline uint32_t swap_dir(uint32_t f) { return ((f & 1u) << 1) | (f >> 1); }
+
+// A triangle {u, v, w}, u < v, found once (from the forward lists of its two
+// first vertices in degree order): w is a shared vertex of each of its three
+// dyads.  f = f_uv relative to u, fa = f_uw relative to u, fb = f_vw relative
+// to v.
+template <class H>
+__device__ inline void on_triangle(uint32_t w, uint32_t fa, uint32_t fb, uint32_t u, uint32_t v, uint32_t f,
+                                   const uint8_t* T, H& h) {
+    const uint32_t sa = swap_dir(fa), sb = swap_dir(fb), sf = swap_dir(f);
+    on_common(w, fa, fb, u, v, f, T, h);                      // dyad (u, v), third vertex w
+    if (u < w) on_common(v, f, sb, u, w, fa, T, h);           // dyad (u, w), third vertex v
+    else on_common(v, sb, f, w, u, sa, T, h);                 // dyad (w, u)
+    if (v < w) on_common(u, sf, sa, v, w, fb, T, h);          // dyad (v, w), third vertex u
+    else on_common(u, sa, sf, w, v, sb, T, h);                // dyad (w, v)
+}
+
+// What a shared vertex of the two rows of a record means: for dyad records a
+// shared neighbour of the dyad; for forward-list edge records a triangle.
+template <bool Tri, class H>
+__device__ inline void on_shared(uint32_t w, uint32_t fa, uint32_t fb, uint32_t u, uint32_t v, uint32_t f,
+                                 const uint8_t* T, H& h) {
+    if constexpr (Tri) on_triangle(w, fa, fb, u, v, f, T, h);
+    else on_common(w, fa, fb, u, v, f, T, h);
 }
 
 __device__ inline dyad_rec load_rec(const dyad_rec* p) {
@@ -139,16 +174,18 @@ constexpr uint32_t kSentinel = 0xffffffffu;
 // memory (L1/L2 resident for the short rows of this bucket).
 constexpr int kLaneB = 256;
 
-template <class H>
+template <bool Tri, class H>
 __device__ inline void lane_dyad(const dyad_rec& r, const uint32_t* __restrict__ nbr, const uint64_t* __restrict__ tpre,
                                  uint64_t n, const uint8_t* T, H& h) {
-    const dyad_totals t = load_totals(r, tpre);
+    dyad_totals t{};
+    if constexpr (!Tri) t = load_totals(r, tpre);
     const uint32_t u = r.u, v = r.vf >> 2, f = r.vf & 3u;
     uint32_t i = r.bu, j = r.bv;
-    // rows are never empty: v is in row u and u is in row v
+    // rows are never empty: v is in row u and u is in row v (dyad records);
+    // edge records with an empty forward list are never emitted
     uint32_t a = nbr[i], b = nbr[j];
     for (;;) {
-        if ((a ^ b) < 4u) on_common(a >> 2, a & 3u, b & 3u, u, v, f, T, h);
+        if ((a ^ b) < 4u) on_shared<Tri>(a >> 2, a & 3u, b & 3u, u, v, f, T, h);
         if (a <= (b | 3u)) {
             if (++i >= r.eu) break;
             a = nbr[i];
@@ -157,19 +194,38 @@ __device__ inline void lane_dyad(const dyad_rec& r, const uint32_t* __restrict__
             b = nbr[j];
         }
     }
-    add_totals(r, t, n, T, h);
+    if constexpr (!Tri) add_totals(r, t, n, T, h);
 }
 
+template <bool Tri>
 __global__ __launch_bounds__(kLaneB) void k_census_lane(census_args L) {
     extern __shared__ unsigned long long lds[];
     __shared__ uint8_t T[64];
-    if (threadIdx.x < 64) T[threadIdx.x] = c_table[threadIdx.x];
+    if (threadIdx.x < 64) T[threadIdx.x] = L.table[threadIdx.x];
     lane_bins<kLaneB> h{lds};
     h.clear();
     __syncthreads();
     for (uint64_t d = (uint64_t)blockIdx.x * kLaneB + threadIdx.x; d < L.count;
          d += (uint64_t)gridDim.x * kLaneB)
-        lane_dyad(load_rec(L.dyads + d), L.nbr, L.tpre, L.n, T, h);
+        lane_dyad<Tri>(load_rec(L.dyads + d), L.nbr, L.tpre, L.n, T, h);
+    h.flush(L.acc);
+}
+
+// The per-dyad terms that need no intersection (the dyadic base and the
+// typed counts of N(u) above v and N(v) above u), one lane per dyad record:
+// with forward-list edge records the shared vertices come from the triangles.
+__global__ __launch_bounds__(kLaneB) void k_census_totals(census_args L) {
+    extern __shared__ unsigned long long lds[];
+    __shared__ uint8_t T[64];
+    if (threadIdx.x < 64) T[threadIdx.x] = L.table[threadIdx.x];
+    lane_bins<kLaneB> h{lds};
+    h.clear();
+    __syncthreads();
+    for (uint64_t d = (uint64_t)blockIdx.x * kLaneB + threadIdx.x; d < L.count;
+         d += (uint64_t)gridDim.x * kLaneB) {
+        const dyad_rec r = load_rec(L.dyads + d);
+        add_totals(r, load_totals(r, L.tpre), L.n, T, h);
+    }
     h.flush(L.acc);
 }
 
@@ -205,7 +261,7 @@ struct wave_sync {
     }
 };
 
-template <int G, int TW, class Sync, class H>
+template <int G, int TW, class Sync, bool Tri, class H>
 __device__ inline void merge_path(const dyad_rec& r, const uint32_t* __restrict__ nbr, uint32_t* sA, uint32_t* sB,
                                   uint32_t* s_xt, uint32_t lane, const uint8_t* T, H& h) {
     constexpr uint32_t PER = TW / G;
@@ -243,7 +299,7 @@ __device__ inline void merge_path(const dyad_rec& r, const uint32_t* __restrict_
 #pragma unroll
             for (uint32_t t = 0; t < PER; ++t) {
                 if (t < steps) {
-                    if ((a ^ b) < 4u) on_common(a >> 2, a & 3u, b & 3u, u, v, f, T, h);
+                    if ((a ^ b) < 4u) on_shared<Tri>(a >> 2, a & 3u, b & 3u, u, v, f, T, h);
                     const bool ta = a <= (b | 3u);
                     i += ta ? 1u : 0u;
                     j += ta ? 0u : 1u;
@@ -276,12 +332,13 @@ constexpr int kWaveB = 64;
 constexpr int kWaveTile = 1024;
 constexpr uint32_t kWaveChunk = 16;
 
+template <bool Tri>
 __global__ __launch_bounds__(kWaveB) void k_census_wave(census_args L, unsigned int* ctr) {
     __shared__ unsigned long long bins[wave_bins<kWaveB>::kWords];
     __shared__ uint8_t T[64];
     __shared__ uint32_t sA[kWaveTile + 1], sB[kWaveTile + 1];
     __shared__ uint32_t s_xt;
-    T[threadIdx.x] = c_table[threadIdx.x];
+    T[threadIdx.x] = L.table[threadIdx.x];
     wave_bins<kWaveB> h{bins};
     h.clear();
     __syncthreads();
@@ -296,9 +353,9 @@ __global__ __launch_bounds__(kWaveB) void k_census_wave(census_args L, unsigned 
         for (uint32_t d = c * kWaveChunk; d < end; ++d) {
             const dyad_rec r = load_rec(L.dyads + d);
             dyad_totals t{};
-            if (threadIdx.x == 0) t = load_totals(r, L.tpre);
-            merge_path<kWaveB, kWaveTile, block_sync>(r, L.nbr, sA, sB, &s_xt, threadIdx.x, T, h);
-            if (threadIdx.x == 0) add_totals(r, t, L.n, T, h);
+            if (!Tri && threadIdx.x == 0) t = load_totals(r, L.tpre);
+            merge_path<kWaveB, kWaveTile, block_sync, Tri>(r, L.nbr, sA, sB, &s_xt, threadIdx.x, T, h);
+            if (!Tri && threadIdx.x == 0) add_totals(r, t, L.n, T, h);
         }
         c = __shfl(cn, 0, 64);
     }
@@ -310,12 +367,13 @@ constexpr int kGroupB = 256;
 constexpr int kGroupTile = 4096;
 constexpr uint32_t kGroupChunk = 2;
 
+template <bool Tri>
 __global__ __launch_bounds__(kGroupB) void k_census_group(census_args L, unsigned int* ctr) {
     __shared__ unsigned long long bins[wave_bins<kGroupB>::kWords];
     __shared__ uint8_t T[64];
     __shared__ uint32_t sA[kGroupTile + 1], sB[kGroupTile + 1];
     __shared__ uint32_t s_xt, s_next;
-    if (threadIdx.x < 64) T[threadIdx.x] = c_table[threadIdx.x];
+    if (threadIdx.x < 64) T[threadIdx.x] = L.table[threadIdx.x];
     wave_bins<kGroupB> h{bins};
     h.clear();
     const uint32_t xcd = blockIdx.x % kXcds;
@@ -329,9 +387,9 @@ __global__ __launch_bounds__(kGroupB) void k_census_group(census_args L, unsigne
         for (uint32_t d = c * kGroupChunk; d < end; ++d) {
             const dyad_rec r = load_rec(L.dyads + d);
             dyad_totals t{};
-            if (threadIdx.x == 0) t = load_totals(r, L.tpre);
-            merge_path<kGroupB, kGroupTile, block_sync>(r, L.nbr, sA, sB, &s_xt, threadIdx.x, T, h);
-            if (threadIdx.x == 0) add_totals(r, t, L.n, T, h);
+            if (!Tri && threadIdx.x == 0) t = load_totals(r, L.tpre);
+            merge_path<kGroupB, kGroupTile, block_sync, Tri>(r, L.nbr, sA, sB, &s_xt, threadIdx.x, T, h);
+            if (!Tri && threadIdx.x == 0) add_totals(r, t, L.n, T, h);
         }
         __syncthreads();
         c = s_next;
@@ -340,6 +398,315 @@ __global__ __launch_bounds__(kGroupB) void k_census_group(census_args L, unsigne
     h.flush(L.acc);
 }
 
+
+// ----------------------------------------------------------------- hub ----
+// Hub dyads, grouped by anchor (their endpoint of larger degree).  A
+// workgroup takes one hub task (up to kHubChunk dyads that share the anchor),
+// stages the anchor's row tile by tile into an LDS hash table (kHubTile
+// entries in kHubSlots slots, linear probing), and streams the other
+// endpoint's row of every dyad of the task against it: each entry of that row
+// is probed once, in the tile whose vertex range holds it.  The anchor row is
+// thus read once per task instead of once per dyad, and the work per dyad is
+// proportional to the smaller degree.
+constexpr int kHubB = 256;
+constexpr uint32_t kHubTile = kHubTileEntries;
+constexpr uint32_t kHubBuckets = kHubTile / 2;           // buckets of 4 slots, mean load 2 entries
+constexpr uint32_t kHubSlots = 4 * kHubBuckets;
+constexpr int kHubBucketBits = __builtin_ctz(kHubBuckets);
+static_assert((kHubBuckets & (kHubBuckets - 1)) == 0, "power-of-two bucket count");
+constexpr uint32_t kEmpty = 0xffffffffu;                 // never an entry (w < 2^23)
+constexpr uint32_t kHubGather = 8;
+constexpr uint32_t kHubFlushAfter = 1u << 26;             // probes per lane between bin flushes
+
+// First position in [lo, hi) of a sorted row whose vertex is >= w.
+__device__ inline uint32_t find_first_ge(const uint32_t* __restrict__ nbr, uint32_t lo, uint32_t hi, uint32_t w) {
+    while (lo < hi) {
+        const uint32_t mid = lo + ((hi - lo) >> 1);
+        if ((nbr[mid] >> 2) < w) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+__device__ inline uint32_t hub_bucket(uint32_t w) { return (w * 0x9E3779B1u) >> (32 - kHubBucketBits); }
+
+// Buckets fill their slots in order, so a bucket whose last slot is empty
+// ends the probe sequence of every vertex that hashes to it or before it.
+__device__ inline void hub_insert(uint32_t* hash, uint32_t e) {
+    uint32_t b = hub_bucket(e >> 2);
+    for (;;) {
+        for (uint32_t s = 0; s < 4; ++s)
+            if (atomicCAS(&hash[4 * b + s], kEmpty, e) == kEmpty) return;
+        b = (b + 1) & (kHubBuckets - 1);
+    }
+}
+
+__device__ inline uint32_t hub_probe(const uint32_t* hash, uint32_t w) {
+    const uint4* h4 = reinterpret_cast<const uint4*>(hash);
+    uint32_t b = hub_bucket(w);
+    for (;;) {
+        const uint4 q = h4[b];
+        if ((q.x >> 2) == w) return q.x;
+        if ((q.y >> 2) == w) return q.y;
+        if ((q.z >> 2) == w) return q.z;
+        if ((q.w >> 2) == w) return q.w;
+        if (q.w == kEmpty) return kEmpty;
+        b = (b + 1) & (kHubBuckets - 1);
+    }
+}
+
+// Exclusive scan of a[0..count) in place on a 256-thread block (count <=
+// 4 * 256); a[count] receives the total.  wsum holds 4 words of LDS.
+__device__ inline void block_scan_u32(uint32_t* a, uint32_t count, uint32_t* wsum) {
+    constexpr uint32_t kPer = kHubChunk / kHubB;
+    const uint32_t tid = threadIdx.x, lane = tid & 63u, wid = tid >> 6;
+    uint32_t loc[kPer], s = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < kPer; ++k) {
+        const uint32_t i = tid * kPer + k;
+        loc[k] = s;
+        s += i < count ? a[i] : 0u;
+    }
+    uint32_t incl = s;
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t y = __shfl_up(incl, o, 64);
+        if ((int)lane >= o) incl += y;
+    }
+    if (lane == 63) wsum[wid] = incl;
+    __syncthreads();
+    uint32_t base = 0, tot = 0;
+    for (uint32_t w = 0; w < kHubB / 64; ++w) {
+        base += w < wid ? wsum[w] : 0u;
+        tot += wsum[w];
+    }
+    base += incl - s;
+#pragma unroll
+    for (uint32_t k = 0; k < kPer; ++k) {
+        const uint32_t i = tid * kPer + k;
+        if (i < count) a[i] = base + loc[k];
+    }
+    if (tid == 0) a[count] = tot;
+    __syncthreads();
+}
+
+// LDS of the hub mode: the hash table, three per-dyad arrays, per-lane 32-bit
+// class bins for the shared vertices (the discard bin takes the misses and is never
+// read), and scan scratch.
+struct hub_lds {
+    uint32_t* hash;   // kHubSlots, 16-byte aligned
+    uint32_t* pos;    // next unprobed position in the other endpoint's row
+    uint32_t* meta;   // (x << 3) | (anchor is u) << 2 | f_uv
+    uint32_t* off;    // probes of this tile, then their exclusive scan (kHubChunk + 1)
+    uint32_t* bins;   // kBins x kHubB
+    uint32_t* wsum;   // 4 words
+    uint32_t* cls;    // 64 packed class triples
+};
+constexpr uint32_t kHubLdsWords = kHubSlots + 2 * kHubChunk + (kHubChunk + 4) + kBins * kHubB + 4 + 64;
+
+__device__ inline hub_lds hub_carve(uint32_t* base) {
+    uint32_t* p = base;
+    hub_lds S;
+    S.hash = p;  p += kHubSlots;
+    S.pos = p;   p += kHubChunk;
+    S.meta = p;  p += kHubChunk;
+    S.off = p;   p += kHubChunk + 4;
+    S.bins = p;  p += kBins * kHubB;
+    S.wsum = p;  p += 4;
+    S.cls = p;
+    return S;
+}
+
+__device__ inline void hub_bins_clear(const hub_lds& S) {
+    for (uint32_t k = threadIdx.x; k < kBins * kHubB; k += kHubB) S.bins[k] = 0;
+}
+
+// Adds the per-lane bins (signed 32-bit differences) to h: each wavefront
+// sums its lanes, lane 0 adds the sums.  Bins are left cleared.
+template <class H>
+__device__ inline void hub_bins_flush(const hub_lds& S, H& h) {
+    __syncthreads();
+    const uint32_t lane = threadIdx.x & 63u;
+    for (uint32_t c = 0; c < kNumClasses; ++c) {
+        long long v = (long long)(int32_t)S.bins[c * kHubB + threadIdx.x];
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        if (lane == 0 && v != 0) h.add(c, (unsigned long long)v);
+        S.bins[c * kHubB + threadIdx.x] = 0;
+    }
+    __syncthreads();
+}
+
+// Class lookup for a shared vertex, packed per (f_uv, f_a, f_b) with f_a the
+// direction bits of the pair (u, w) and f_b those of (v, w), one byte each:
+// T[f_uv | f_a << 2 | f_b << 4] (its full code), T[f_uv | f_a << 2] (the
+// u-only code it must not be counted under), T[f_uv | f_b << 4] (the v-only
+// code) and T[f_uv] (the dyadic code whose count grows by one).
+__device__ inline void hub_fill_cls(const hub_lds& S, const uint8_t* T) {
+    for (uint32_t k = threadIdx.x; k < 64; k += blockDim.x) {
+        const uint32_t f = k & 3u, fa = (k >> 2) & 3u, fb = k >> 4;
+        S.cls[k] = (uint32_t)T[k] | ((uint32_t)T[f | (fa << 2)] << 8) | ((uint32_t)T[f | (fb << 4)] << 16) |
+                   ((uint32_t)T[f] << 24);
+    }
+}
+
+// One hub task on the whole workgroup (kHubB threads).  Per tile of the
+// anchor row: clear and fill the hash table; count, for every dyad, the
+// entries of the other row that fall in the tile's vertex range; scan the
+// counts; then every lane probes an equal contiguous slice of the flattened
+// (dyad, entry) list with kHubGather gathers in flight.  The shared-vertex
+// bookkeeping is branch-free: every probe adds to four lane-private bins
+// (misses to the discard bin).
+// 32-bit lane-private bins of the hub mode as a histogram (a triangle's
+// updates; each changes a bin by one).
+struct hub_lane_bins {
+    uint32_t* my;
+    __device__ inline void add(uint32_t cls, unsigned long long x) { atomicAdd(&my[cls * kHubB], (uint32_t)x); }
+};
+
+template <bool Tri, class H>
+__device__ inline void hub_task_run(const hub_task& tk, const dyad_rec* __restrict__ dyads,
+                                    const uint32_t* __restrict__ nbr, const uint64_t* __restrict__ tpre, uint64_t n,
+                                    uint32_t u_lo, uint32_t u_hi, const hub_lds& S, const uint8_t* T, H& h,
+                                    uint32_t& since) {
+    const uint32_t tid = threadIdx.x;
+    const uint32_t nrec = tk.end - tk.begin, a = tk.anchor;
+    uint32_t* my_bins = S.bins + tid;
+    const dyad_rec r0 = load_rec(dyads + tk.begin);
+    const uint32_t hb = r0.u == a ? r0.bu : r0.bv, he = r0.u == a ? r0.eu : r0.ev;
+    const bool multi_tile = he - hb > kHubTile;
+    for (uint32_t i = tid; i < nrec; i += kHubB) {
+        const dyad_rec r = load_rec(dyads + tk.begin + i);
+        const bool anchor_u = r.u == a;
+        const uint32_t x = anchor_u ? (r.vf >> 2) : r.u;
+        const uint32_t xb = anchor_u ? r.bv : r.bu, xe = anchor_u ? r.ev : r.eu;
+        const bool in = r.u >= u_lo && r.u < u_hi;
+        S.pos[i] = in ? xb : xe;   // outside the requested range: nothing to probe
+        S.meta[i] = (x << 3) | (anchor_u ? 4u : 0u) | (r.vf & 3u);
+        if (!multi_tile) S.off[i] = in ? xe - xb : 0u;
+        if (!Tri && in) add_totals(r, load_totals(r, tpre), n, T, h);
+    }
+    for (uint32_t tb = hb; tb < he; tb += kHubTile) {
+        const uint32_t te = min(he, tb + kHubTile);
+        for (uint32_t k = tid; k < kHubSlots; k += kHubB) S.hash[k] = kEmpty;
+        __syncthreads();
+        for (uint32_t k = tb + tid; k < te; k += kHubB) hub_insert(S.hash, nbr[k]);
+        if (multi_tile) {
+            const uint32_t w_end = te < he ? (nbr[te] >> 2) : kEmpty;
+            for (uint32_t i = tid; i < nrec; i += kHubB) {
+                const uint32_t p0 = S.pos[i];
+                uint32_t xe = p0;
+                if (p0 != 0xffffffffu) {
+                    const dyad_rec r = load_rec(dyads + tk.begin + i);
+                    xe = r.u == a ? r.ev : r.eu;
+                }
+                const uint32_t p1 = w_end == kEmpty ? xe : find_first_ge(nbr, p0, xe, w_end);
+                S.off[i] = p1 - p0;
+            }
+        }
+        __syncthreads();
+        block_scan_u32(S.off, nrec, S.wsum);
+        const uint32_t P = S.off[nrec];
+        const uint32_t per = (P + kHubB - 1) / kHubB;
+        const uint32_t f0 = min(P, tid * per), f1 = min(P, f0 + per);
+        if (f0 < f1) {
+            uint32_t lo = 0, hi = nrec;                 // record holding f0: off[i] <= f0 < off[i+1]
+            while (hi - lo > 1) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (S.off[mid] <= f0) lo = mid; else hi = mid;
+            }
+            uint32_t i = lo;
+            uint32_t next = S.off[i + 1], base = S.pos[i] - S.off[i], m = S.meta[i];
+            for (uint32_t f = f0; f < f1; f += kHubGather) {
+                uint32_t e[kHubGather], mk[kHubGather];
+#pragma unroll
+                for (uint32_t k = 0; k < kHubGather; ++k) {
+                    const uint32_t ff = f + k;
+                    e[k] = kEmpty;
+                    mk[k] = m;
+                    if (ff < f1) {
+                        if (ff >= next) {
+                            do {
+                                ++i;
+                                next = S.off[i + 1];
+                            } while (ff >= next);
+                            base = S.pos[i] - S.off[i];
+                            m = S.meta[i];
+                        }
+                        mk[k] = m;
+                        e[k] = nbr[base + ff];
+                    }
+                }
+#pragma unroll
+                for (uint32_t k = 0; k < kHubGather; ++k) {
+                    const uint32_t hit = e[k] != kEmpty ? hub_probe(S.hash, e[k] >> 2) : kEmpty;
+                    const bool miss = hit == kEmpty;
+                    const uint32_t x = mk[k] >> 3, fuv = mk[k] & 3u;
+                    const bool anchor_u = (mk[k] & 4u) != 0;
+                    const uint32_t u = anchor_u ? a : x, v = anchor_u ? x : a, w = e[k] >> 2;
+                    const uint32_t fx = e[k] & 3u, fh = hit & 3u;
+                    const uint32_t fa = anchor_u ? fh : fx, fb = anchor_u ? fx : fh;
+                    if constexpr (Tri) {
+                        if (!miss) {
+                            hub_lane_bins lb{my_bins};
+                            on_triangle(w, fa, fb, u, v, fuv, T, lb);
+                        }
+                    } else {
+                        const bool gv = !miss && w > v, gu = !miss && w > u;
+                        const uint32_t c3 = S.cls[fuv | (fa << 2) | (fb << 4)];
+                        const uint32_t b0 = miss ? kDiscard : c3 >> 24;
+                        const uint32_t b1 = gv ? c3 & 255u : kDiscard;
+                        const uint32_t b2 = gv ? (c3 >> 8) & 255u : kDiscard;
+                        const uint32_t b3 = gu ? (c3 >> 16) & 255u : kDiscard;
+                        atomicAdd(&my_bins[b0 * kHubB], 1u);
+                        atomicAdd(&my_bins[b1 * kHubB], 1u);
+                        atomicAdd(&my_bins[b2 * kHubB], 0xffffffffu);
+                        atomicAdd(&my_bins[b3 * kHubB], 0xffffffffu);
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        if (multi_tile)
+            for (uint32_t i = tid; i < nrec; i += kHubB) S.pos[i] += S.off[i + 1] - S.off[i];
+        // A lane's 32-bit bins change by at most one per probe: flush them long
+        // before 2^31 probes (`per` is the same on every lane of the workgroup).
+        since += per;
+        if (since >= kHubFlushAfter) {
+            hub_bins_flush(S, h);
+            since = 0;
+        }
+        __syncthreads();
+    }
+}
+
+template <bool Tri>
+__global__ __launch_bounds__(kHubB) void k_census_hub(census_args L, const hub_task* __restrict__ tasks,
+                                                      uint32_t ntasks, unsigned int* ctr) {
+    __shared__ __attribute__((aligned(16))) uint32_t hub_words[kHubLdsWords];
+    __shared__ unsigned long long bins[wave_bins<kHubB>::kWords];
+    __shared__ uint8_t T[64];
+    __shared__ uint32_t s_next;
+    if (threadIdx.x < 64) T[threadIdx.x] = L.table[threadIdx.x];
+    wave_bins<kHubB> h{bins};
+    h.clear();
+    const hub_lds S = hub_carve(hub_words);
+    hub_bins_clear(S);
+    __syncthreads();
+    hub_fill_cls(S, T);
+    uint32_t since = 0;
+    const uint32_t xcd = blockIdx.x % kXcds;
+    if (threadIdx.x == 0) s_next = take_chunk(ctr, xcd);
+    __syncthreads();
+    uint32_t t = s_next;
+    __syncthreads();
+    while (t < ntasks) {
+        if (threadIdx.x == 0) s_next = take_chunk(ctr, xcd);
+        hub_task_run<Tri>(tasks[t], L.dyads, L.nbr, L.tpre, L.n, L.u_lo, L.u_hi, S, T, h, since);
+        __syncthreads();
+        t = s_next;
+        __syncthreads();
+    }
+    hub_bins_flush(S, h);
+    h.flush(L.acc);
+}
 
 // --------------------------------------------------------------- batch ----
 // One persistent launch over the work items of many resident graphs.  A
@@ -351,20 +718,22 @@ __global__ __launch_bounds__(kGroupB) void k_census_group(census_args L, unsigne
 constexpr int kBatchB = 256;
 constexpr int kBatchWaveTile = 512;
 constexpr int kBatchGroupTile = 2048;
-constexpr int kBatchTileWords = (4 * 2 * (kBatchWaveTile + 1) > 2 * (kBatchGroupTile + 1))
-                                    ? 4 * 2 * (kBatchWaveTile + 1) : 2 * (kBatchGroupTile + 1);
+constexpr int kBatchMergeWords = (4 * 2 * (kBatchWaveTile + 1) > 2 * (kBatchGroupTile + 1))
+                                     ? 4 * 2 * (kBatchWaveTile + 1) : 2 * (kBatchGroupTile + 1);
+constexpr int kBatchHubWords = (int)kHubLdsWords;
+constexpr int kBatchTileWords = kBatchMergeWords > kBatchHubWords ? kBatchMergeWords : kBatchHubWords;
 
 __global__ __launch_bounds__(kBatchB) void k_census_batch(const graph_desc* __restrict__ G,
                                                           const work_item* __restrict__ items,
                                                           const uint32_t* __restrict__ num_items,
                                                           unsigned long long* __restrict__ accs,
                                                           unsigned int* __restrict__ ctr) {
-    extern __shared__ unsigned long long lds[];
+    __shared__ __attribute__((aligned(16))) uint32_t tiles[kBatchTileWords];
+    __shared__ unsigned long long bins[wave_bins<kBatchB>::kWords];
     __shared__ uint8_t T[64];
-    __shared__ uint32_t tiles[kBatchTileWords];
     __shared__ uint32_t s_xt[kBatchB / 64], s_next;
     if (threadIdx.x < 64) T[threadIdx.x] = c_table[threadIdx.x];
-    lane_bins<kBatchB> h{lds};
+    wave_bins<kBatchB> h{bins};
     h.clear();
     const uint32_t count = *num_items;
     const uint32_t xcd = blockIdx.x % kXcds;
@@ -389,7 +758,7 @@ __global__ __launch_bounds__(kBatchB) void k_census_batch(const graph_desc* __re
         const graph_desc g = G[it.graph];
         if (it.kind == kItemLane) {
             const uint32_t d = it.begin + tid;
-            if (d < it.end) lane_dyad(load_rec(g.dyads + d), g.nbr, g.tpre, g.n, T, h);
+            if (d < it.end) lane_dyad<false>(load_rec(g.dyads + d), g.nbr, g.tpre, g.n, T, h);
         } else if (it.kind == kItemWave) {
             uint32_t* sA = tiles + wid * 2 * (kBatchWaveTile + 1);
             uint32_t* sB = sA + kBatchWaveTile + 1;
@@ -397,16 +766,26 @@ __global__ __launch_bounds__(kBatchB) void k_census_batch(const graph_desc* __re
                 const dyad_rec r = load_rec(g.dyads + d);
                 dyad_totals t{};
                 if (lane == 0) t = load_totals(r, g.tpre);
-                merge_path<64, kBatchWaveTile, wave_sync>(r, g.nbr, sA, sB, &s_xt[wid], lane, T, h);
+                merge_path<64, kBatchWaveTile, wave_sync, false>(r, g.nbr, sA, sB, &s_xt[wid], lane, T, h);
                 if (lane == 0) add_totals(r, t, g.n, T, h);
             }
-        } else {
+        } else if (it.kind == kItemGroup) {
             const dyad_rec r = load_rec(g.dyads + it.begin);
             dyad_totals t{};
             if (tid == 0) t = load_totals(r, g.tpre);
-            merge_path<kBatchB, kBatchGroupTile, block_sync>(r, g.nbr, tiles, tiles + kBatchGroupTile + 1, &s_xt[0],
+            merge_path<kBatchB, kBatchGroupTile, block_sync, false>(r, g.nbr, tiles, tiles + kBatchGroupTile + 1, &s_xt[0],
                                                               tid, T, h);
             if (tid == 0) add_totals(r, t, g.n, T, h);
+        } else {
+            const hub_lds S = hub_carve(tiles);
+            hub_bins_clear(S);
+            hub_fill_cls(S, T);
+            uint32_t since = 0;
+            for (uint32_t k = it.begin; k < it.end; ++k) {
+                hub_task_run<false>(g.hub_tasks[k], g.dyads, g.nbr, g.tpre, g.n, 0u, 0xffffffffu, S, T, h, since);
+                __syncthreads();
+            }
+            hub_bins_flush(S, h);
         }
         __syncthreads();
         idx = s_next;
@@ -436,8 +815,7 @@ hipError_t batch_launch(const graph_desc* descs, const work_item* items, const u
     uint32_t zb = (uint32_t)std::min<uint64_t>((acc_words + 255) / 256, 1024);
     hipLaunchKernelGGL(k_fill_u64_grid, dim3(zb ? zb : 1), dim3(256), 0, s, accs, acc_words);
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, counters, kXcds);
-    hipLaunchKernelGGL(k_census_batch, dim3(grid), dim3(kBatchB), sizeof(unsigned long long) * lane_bins<kBatchB>::kWords,
-                       s, descs, items, num_items, accs, counters);
+    hipLaunchKernelGGL(k_census_batch, dim3(grid), dim3(kBatchB), 0, s, descs, items, num_items, accs, counters);
     return hipGetLastError();
 }
 
@@ -445,25 +823,67 @@ hipError_t census_upload_table() {
     return hipMemcpyToSymbol(HIP_SYMBOL(c_table), kTable.t, sizeof(kTable.t));
 }
 
-hipError_t census_launch(const device_graph& g, const census_slices& sl, unsigned long long* acc,
-                         unsigned int* counters, const census_config& cfg, hipStream_t s, hipEvent_t* ev) {
+namespace {
+
+template <bool Tri>
+void launch_bucket(int b, const census_args& L, uint64_t cnt, const census_config& cfg, unsigned int* counters,
+                   hipStream_t s) {
+    if (b == 0) {
+        uint32_t grid = (uint32_t)std::min<uint64_t>((cnt + kLaneB - 1) / kLaneB, cfg.lane_blocks);
+        size_t sh = sizeof(unsigned long long) * lane_bins<kLaneB>::kWords;
+        hipLaunchKernelGGL(k_census_lane<Tri>, dim3(grid), dim3(kLaneB), sh, s, L);
+    } else if (b == 1) {
+        uint32_t grid = (uint32_t)std::min<uint64_t>(cnt, cfg.wave_blocks);
+        hipLaunchKernelGGL(k_census_wave<Tri>, dim3(grid), dim3(kWaveB), 0, s, L, counters + kXcds);
+    } else if (b == 2) {
+        uint32_t grid = (uint32_t)std::min<uint64_t>(cnt, cfg.group_blocks);
+        hipLaunchKernelGGL(k_census_group<Tri>, dim3(grid), dim3(kGroupB), 0, s, L, counters + 2 * kXcds);
+    }
+}
+
+template <bool Tri>
+void launch_hub(const census_args& L, const hub_task* tasks, uint32_t ntasks, const census_config& cfg,
+                unsigned int* counters, hipStream_t s) {
+    uint32_t grid = (uint32_t)std::min<uint64_t>(ntasks, cfg.hub_blocks);
+    hipLaunchKernelGGL(k_census_hub<Tri>, dim3(grid), dim3(kHubB), 0, s, L, tasks, ntasks, counters + 3 * kXcds);
+}
+
+}  // namespace
+
+hipError_t census_launch(const device_graph& g, const census_slices& sl, bool tri, const uint8_t* table,
+                         unsigned long long* acc, unsigned int* counters, const census_config& cfg, hipStream_t s,
+                         hipEvent_t* ev) {
     hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, acc, kNumClasses);
-    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, counters, 3 * kXcds);
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, counters, kBuckets * kXcds);
+    const dyad_rec* recs = tri ? g.tri.edges.recs : g.dyads;
+    const uint32_t* nbr = tri ? g.tri.fwd : g.nbr;
+    const hub_task* tasks = tri ? g.tri.edges.tasks : g.hub_tasks;
+    const uint32_t ntasks = tri ? g.tri.edges.n_tasks : g.n_hub_tasks;
+    if (tri) {
+        if (ev) (void)hipEventRecord(ev[2 * kBuckets], s);
+        if (g.p > 0) {
+            census_args L{g.dyads, (uint32_t)g.p, g.nbr, g.tpre, (uint64_t)g.n, acc, 0u, 0xffffffffu, table};
+            uint32_t grid = (uint32_t)std::min<uint64_t>((g.p + kLaneB - 1) / kLaneB, cfg.lane_blocks);
+            size_t sh = sizeof(unsigned long long) * lane_bins<kLaneB>::kWords;
+            hipLaunchKernelGGL(k_census_totals, dim3(grid), dim3(kLaneB), sh, s, L);
+        }
+        if (ev) (void)hipEventRecord(ev[2 * kBuckets + 1], s);
+    }
     for (int b = 0; b < kBuckets; ++b) {
         uint64_t cnt = sl.end[b] > sl.begin[b] ? sl.end[b] - sl.begin[b] : 0;
+        if (b == kBucketHub) cnt = ntasks;
         if (ev) (void)hipEventRecord(ev[2 * b], s);
         if (cnt > 0) {
-            census_args L{g.dyads + sl.begin[b], (uint32_t)cnt, g.nbr, g.tpre, (uint64_t)g.n, acc};
-            if (b == 0) {
-                uint32_t grid = (uint32_t)std::min<uint64_t>((cnt + kLaneB - 1) / kLaneB, cfg.lane_blocks);
-                size_t sh = sizeof(unsigned long long) * lane_bins<kLaneB>::kWords;
-                hipLaunchKernelGGL(k_census_lane, dim3(grid), dim3(kLaneB), sh, s, L);
-            } else if (b == 1) {
-                uint32_t grid = (uint32_t)std::min<uint64_t>(cnt, cfg.wave_blocks);
-                hipLaunchKernelGGL(k_census_wave, dim3(grid), dim3(kWaveB), 0, s, L, counters + kXcds);
+            census_args L{recs + sl.begin[b], (uint32_t)cnt, nbr, g.tpre, (uint64_t)g.n, acc, sl.u_lo, sl.u_hi,
+                          table};
+            if (b == kBucketHub) {
+                L.dyads = recs;
+                if (tri) launch_hub<true>(L, tasks, ntasks, cfg, counters, s);
+                else launch_hub<false>(L, tasks, ntasks, cfg, counters, s);
+            } else if (tri) {
+                launch_bucket<true>(b, L, cnt, cfg, counters, s);
             } else {
-                uint32_t grid = (uint32_t)std::min<uint64_t>(cnt, cfg.group_blocks);
-                hipLaunchKernelGGL(k_census_group, dim3(grid), dim3(kGroupB), 0, s, L, counters + 2 * kXcds);
+                launch_bucket<false>(b, L, cnt, cfg, counters, s);
             }
         }
         if (ev) (void)hipEventRecord(ev[2 * b + 1], s);

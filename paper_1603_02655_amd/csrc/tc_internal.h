@@ -9,7 +9,10 @@
 //                         [a, b) of a row holds lo(tpre[b]-tpre[a]) arcs leaving
 //                         the owner and hi(...) arcs entering it
 //   dyads[p]      dyad_rec one task per canonical dyad (u < v joined either way),
-//                         u-major, partitioned into degree buckets
+//                         partitioned into degree buckets; u-major inside the
+//                         merge buckets, anchor-major inside the hub bucket
+//   hub_tasks[]   hub_task runs of at most kHubChunk hub-bucket records that
+//                         share their anchor (the endpoint of larger degree)
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -17,7 +20,8 @@
 namespace tc {
 
 constexpr int kNumClasses = 16;
-constexpr int kBuckets = 3;            // lane, wave, group
+constexpr int kBuckets = 4;            // lane, wave, group (canonical-order merges), hub (anchor-major)
+constexpr int kBucketHub = 3;
 constexpr int kMaxN = 4801280;         // largest n with C(n,3) < 2^64
 
 // One canonical dyad (u, v), u < v.  All indices are global positions in nbr.
@@ -30,6 +34,21 @@ struct __attribute__((aligned(16))) dyad_rec {
     uint32_t vf;       // (v << 2) | f_uv, f_uv = IsEdge(u,v) + 2 IsEdge(v,u)
 };
 static_assert(sizeof(dyad_rec) == 32, "dyad record is two 16-byte loads");
+
+// A run of hub-bucket records [begin, end) whose dyads all contain `anchor`.
+struct hub_task {
+    uint32_t begin, end, anchor, pad;
+};
+constexpr uint32_t kHubChunk = 1024;          // records per hub task
+constexpr uint32_t kHubTileEntries = 2048;    // anchor-row entries staged per LDS tile
+
+// Bucket thresholds.  Dyads with max(|N(u)|, |N(v)|) >= t_hub go to the hub
+// bucket (anchored at the larger-degree endpoint, ties to the larger id); the
+// others by k = |N(u)| + |N(v)| - 2: lane if k < t0, wave if k < t1, else group.
+struct bucket_params {
+    uint32_t t0, t1, t_hub;
+    uint32_t tri;   // also build the degree-ordered forward lists and their edge records
+};
 
 // ---------------------------------------------------------------------------
 // 64 -> 16 class table, derived here from the naming rules of the 16 classes
@@ -100,12 +119,14 @@ static_assert(kTable.t[0] == 0 && kTable.t[63] == 15, "table endpoints");
 // kernels launched from the host side (definitions in tc_build.hip / tc_census.hip)
 // ---------------------------------------------------------------------------
 struct census_args {
-    const dyad_rec* dyads;    // bucket slice
+    const dyad_rec* dyads;    // bucket slice (the whole record array for the hub kernel)
     uint32_t count;           // dyads in the slice
     const uint32_t* nbr;
     const uint64_t* tpre;
     uint64_t n;               // vertices of the graph
     unsigned long long* acc;  // 16 accumulators of the graph
+    uint32_t u_lo, u_hi;      // hub kernel: only dyads with u in [u_lo, u_hi)
+    const uint8_t* table;     // 64 bin indices (device memory), one per code
 };
 
 // device scan / sort helpers (tc_build.hip)

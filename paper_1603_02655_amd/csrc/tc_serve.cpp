@@ -99,7 +99,7 @@ uint64_t job_footprint(const job& j) {
     uint64_t ws = sizeof(unsigned long long) * kNumClasses + sizeof(graph_desc);
     if (!j.cold) {
         const device_graph& g = j.g->g;
-        uint64_t items = (g.bucket_off[3] - g.bucket_off[2]) +
+        uint64_t items = g.n_hub_tasks + (g.bucket_off[3] - g.bucket_off[2]) +
                          (g.bucket_off[2] - g.bucket_off[1] + kBatchWavePerItem - 1) / kBatchWavePerItem +
                          (g.bucket_off[1] - g.bucket_off[0] + kBatchLanePerItem - 1) / kBatchLanePerItem;
         return ws + sizeof(work_item) * items;
@@ -195,8 +195,10 @@ bool launch_round(serve_state* S, int si) {
     tc_context_s* ctx = S->ctx;
     for (job* j : s.jobs) {
         if (!j->cold) continue;
-        j->status = build_into(j->n, (int64_t)j->src.size(), j->src.data(), j->dst.data(), j->flags,
-                               ctx->tuning.t0, ctx->tuning.t1, s.stream, &j->built, nullptr);
+        bucket_params bp = params_of(ctx->tuning);
+        bp.tri = 0;   // served graphs run through the batched kernel, which uses the dyad records
+        j->status = build_into(j->n, (int64_t)j->src.size(), j->src.data(), j->dst.data(), j->flags, bp, s.stream,
+                               &j->built, nullptr);
         std::vector<int32_t>().swap(j->src);
         std::vector<int32_t>().swap(j->dst);
     }
@@ -205,11 +207,11 @@ bool launch_round(serve_state* S, int si) {
     for (size_t i = 0; i < s.jobs.size(); ++i) {
         job* j = s.jobs[i];
         if (j->status != TC_OK) {
-            descs[i] = graph_desc{nullptr, nullptr, nullptr, 0};
+            descs[i] = graph_desc{nullptr, nullptr, nullptr, 0, nullptr, 0};
             continue;
         }
         const device_graph& g = j->cold ? j->built : j->g->g;
-        descs[i] = graph_desc{g.dyads, g.nbr, g.tpre, (uint64_t)g.n};
+        descs[i] = graph_desc{g.dyads, g.nbr, g.tpre, (uint64_t)g.n, g.hub_tasks, 0};
         append_items(g, (uint32_t)i, items);
     }
     hipError_t e = slot_reserve(s, (uint32_t)s.jobs.size(), (uint32_t)items.size());

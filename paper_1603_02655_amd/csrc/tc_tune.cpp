@@ -60,13 +60,14 @@ bool cache_lookup(const std::string& text, const std::string& key, tc_tuning* t)
     p = text.find('{', p + needle.size());
     if (p == std::string::npos) return false;
     unsigned a[6];
+    unsigned b[3];
     int got = std::sscanf(text.c_str() + p,
                           "{\"t0\": %u, \"t1\": %u, \"lane_blocks\": %u, \"wave_blocks\": %u, \"group_blocks\": %u, "
-                          "\"batch_blocks\": %u",
-                          &a[0], &a[1], &a[2], &a[3], &a[4], &a[5]);
-    if (got != 6) return false;
-    *t = tc_tuning{a[0], a[1], a[2], a[3], a[4], a[5]};
-    return t->t0 <= t->t1 && a[2] && a[3] && a[4] && a[5];
+                          "\"batch_blocks\": %u, \"t_hub\": %u, \"hub_blocks\": %u, \"tri\": %u",
+                          &a[0], &a[1], &a[2], &a[3], &a[4], &a[5], &b[0], &b[1], &b[2]);
+    if (got != 9) return false;
+    *t = tc_tuning{a[0], a[1], a[2], a[3], a[4], a[5], b[0], b[1], b[2]};
+    return t->t0 <= t->t1 && a[2] && a[3] && a[4] && a[5] && b[1] && b[2] <= 1;
 }
 
 void cache_store(const char* path, const std::string& key, const tc_tuning& t, double seconds) {
@@ -74,8 +75,9 @@ void cache_store(const char* path, const std::string& key, const tc_tuning& t, d
     char entry[512];
     std::snprintf(entry, sizeof(entry),
                   "\"%s\": {\"t0\": %u, \"t1\": %u, \"lane_blocks\": %u, \"wave_blocks\": %u, \"group_blocks\": %u, "
-                  "\"batch_blocks\": %u, \"seconds\": %.6g}",
-                  key.c_str(), t.t0, t.t1, t.lane_blocks, t.wave_blocks, t.group_blocks, t.batch_blocks, seconds);
+                  "\"batch_blocks\": %u, \"t_hub\": %u, \"hub_blocks\": %u, \"tri\": %u, \"seconds\": %.6g}",
+                  key.c_str(), t.t0, t.t1, t.lane_blocks, t.wave_blocks, t.group_blocks, t.batch_blocks, t.t_hub,
+                  t.hub_blocks, t.tri, seconds);
     size_t close = text.rfind('}');
     std::string out;
     if (text.empty() || close == std::string::npos || text.find('{') == std::string::npos) {
@@ -144,16 +146,22 @@ extern "C" int tc_autotune(tc_context ctx, const tc_graph* sample, int32_t count
     const std::vector<uint32_t> wave = {cu * 5, cu * 10, cu * 20};
     const std::vector<uint32_t> group = {cu * 1, cu * 2, cu * 4};
     const std::vector<uint32_t> batch = {cu * 2, cu * 3, cu * 4, cu * 6};
+    const std::vector<uint32_t> hubt = {32, 64, 128, 256, 512, 1024, 4096, kInf};
+    const std::vector<uint32_t> hubb = {cu * 1, cu * 2, cu * 3, cu * 4};
+    const std::vector<uint32_t> tris = {0, 1};
     const int reps = 2;
 
     rc = apply(ctx, sample, count, best);
     double best_s = 0;
     if (rc == TC_OK) rc = measure(ctx, sample, count, reps, &best_s);
     for (int sweep = 0; sweep < 2 && rc == TC_OK; ++sweep) {
-        for (int param = 0; param < 6 && rc == TC_OK; ++param) {
+        for (int param = -1; param < 8 && rc == TC_OK; ++param) {
             const std::vector<uint32_t>* cands = nullptr;
+            if (param == -1 && count == 1) cands = &tris;   // the batched kernel has no forward-list path
             if (param == 0) cands = &t1s;
             if (param == 1) cands = &t0s;
+            if (param == 6) cands = &hubt;
+            if (param == 7 && count == 1) cands = &hubb;
             if (count == 1) {
                 if (param == 2) cands = &lane;
                 if (param == 3) cands = &wave;
@@ -164,8 +172,9 @@ extern "C" int tc_autotune(tc_context ctx, const tc_graph* sample, int32_t count
             if (!cands) continue;
             for (uint32_t v : *cands) {
                 tc_tuning c = best;
-                uint32_t* field = param == 0 ? &c.t1 : param == 1 ? &c.t0 : param == 2 ? &c.lane_blocks
-                                : param == 3 ? &c.wave_blocks : param == 4 ? &c.group_blocks : &c.batch_blocks;
+                uint32_t* field = param == -1 ? &c.tri : param == 0 ? &c.t1 : param == 1 ? &c.t0 : param == 2 ? &c.lane_blocks
+                                : param == 3 ? &c.wave_blocks : param == 4 ? &c.group_blocks
+                                : param == 5 ? &c.batch_blocks : param == 6 ? &c.t_hub : &c.hub_blocks;
                 if (*field == v) continue;
                 *field = v;
                 if (c.t0 > c.t1) continue;

@@ -36,7 +36,8 @@ TC_BUILD_DEVICE_PTRS = 2
 
 CLASS_NAMES = ("003", "012", "102", "021D", "021U", "021C", "111D", "111U",
                "030T", "030C", "201", "120D", "120U", "120C", "210", "300")
-BUCKETS = ("lane", "wave", "group")
+BUCKETS = ("lane", "wave", "group", "hub")
+NB = len(BUCKETS)
 
 
 class TcError(RuntimeError):
@@ -51,29 +52,35 @@ class tc_graph_info(ctypes.Structure):
                 ("self_loops_dropped", ctypes.c_int64), ("duplicates_dropped", ctypes.c_int64),
                 ("asym_dyads", ctypes.c_int64), ("mutual_dyads", ctypes.c_int64),
                 ("max_degree", ctypes.c_int64), ("device_bytes", ctypes.c_uint64),
-                ("sum_d2", ctypes.c_uint64), ("bucket_dyads", ctypes.c_uint64 * 3),
-                ("bucket_cost", ctypes.c_uint64 * 3)]
+                ("sum_d2", ctypes.c_uint64), ("bucket_dyads", ctypes.c_uint64 * 4),
+                ("bucket_cost", ctypes.c_uint64 * 4), ("hub_tasks", ctypes.c_uint64),
+                ("hub_stream", ctypes.c_uint64), ("hub_staged", ctypes.c_uint64),
+                ("fwd_entries", ctypes.c_uint64), ("tri_bucket_edges", ctypes.c_uint64 * 4),
+                ("tri_bucket_cost", ctypes.c_uint64 * 4), ("tri_tasks", ctypes.c_uint64),
+                ("tri_stream", ctypes.c_uint64), ("tri_staged", ctypes.c_uint64)]
 
     def as_dict(self) -> dict:
         d = {k: getattr(self, k) for k, _ in self._fields_}
-        d["bucket_dyads"] = list(self.bucket_dyads)
-        d["bucket_cost"] = list(self.bucket_cost)
+        for k in ("bucket_dyads", "bucket_cost", "tri_bucket_edges", "tri_bucket_cost"):
+            d[k] = list(getattr(self, k))
         return d
 
 
 class tc_tuning(ctypes.Structure):
     _fields_ = [("t0", ctypes.c_uint32), ("t1", ctypes.c_uint32), ("lane_blocks", ctypes.c_uint32),
                 ("wave_blocks", ctypes.c_uint32), ("group_blocks", ctypes.c_uint32),
-                ("batch_blocks", ctypes.c_uint32)]
+                ("batch_blocks", ctypes.c_uint32), ("t_hub", ctypes.c_uint32), ("hub_blocks", ctypes.c_uint32),
+                ("tri", ctypes.c_uint32)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class tc_kernel_stats(ctypes.Structure):
-    _fields_ = [("ms", ctypes.c_double * 3), ("launches", ctypes.c_uint64 * 3),
+    _fields_ = [("ms", ctypes.c_double * 4), ("launches", ctypes.c_uint64 * 4),
                 ("census_calls", ctypes.c_uint64), ("batch_ms", ctypes.c_double),
-                ("batch_launches", ctypes.c_uint64)]
+                ("batch_launches", ctypes.c_uint64), ("totals_ms", ctypes.c_double),
+                ("totals_launches", ctypes.c_uint64)]
 
 
 class tc_serve_stats(ctypes.Structure):
@@ -98,6 +105,7 @@ SIGNATURES = {
     "tc_graph_release": (ctypes.c_int, [_vp, _vp]),
     "tc_census": (ctypes.c_int, [_vp, _vp, _vp]),
     "tc_census_range": (ctypes.c_int, [_vp, _vp, _i32, _i32, _vp]),
+    "tc_census64": (ctypes.c_int, [_vp, _vp, _vp]),
     "tc_census_batch": (ctypes.c_int, [_vp, _vp, _i32, _vp]),
     "tc_census_each": (ctypes.c_int, [_vp, _vp, _i32, _vp]),
     "tc_submit": (ctypes.c_int, [_vp, _vp, _P(_u64)]),
@@ -271,6 +279,11 @@ class Context:
         _check(load().tc_census(self.handle, g.handle, out.ctypes.data), "tc_census")
         return out
 
+    def census64(self, g: Graph) -> np.ndarray:
+        out = _u64_out(64)
+        _check(load().tc_census64(self.handle, g.handle, out.ctypes.data), "tc_census64")
+        return out
+
     def census_range(self, g: Graph, u0: int, u1: int) -> np.ndarray:
         out = _u64_out(16)
         _check(load().tc_census_range(self.handle, g.handle, int(u0), int(u1), out.ctypes.data), "tc_census_range")
@@ -357,7 +370,8 @@ class Context:
         s = tc_kernel_stats()
         _check(load().tc_get_kernel_stats(self.handle, ctypes.byref(s)), "tc_get_kernel_stats")
         return {"ms": list(s.ms), "launches": list(s.launches), "census_calls": s.census_calls,
-                "batch_ms": s.batch_ms, "batch_launches": s.batch_launches}
+                "batch_ms": s.batch_ms, "batch_launches": s.batch_launches,
+                "totals_ms": s.totals_ms, "totals_launches": s.totals_launches}
 
     def reset_kernel_stats(self):
         _check(load().tc_reset_kernel_stats(self.handle), "tc_reset_kernel_stats")

@@ -2,7 +2,8 @@
 
 Integer work, so every comparison is bit-exact (tolerance 0).  Each graph is
 checked in the default bucket configuration and with every dyad forced into one
-execution mode (lane, wave, group).  At full workload sizes, where the oracle
+execution mode (lane, wave, group, hub), and again through the triangles of the
+degree-ordered forward lists with every edge record forced into each mode.  At full workload sizes, where the oracle
 cannot run the whole graph, the census is checked through the exact degree
 identities and against the oracle's task-queue (vertex range) partial census on
 sampled ranges, and the partials of a partition must sum to the full census.
@@ -23,9 +24,15 @@ pytestmark = pytest.mark.gpu
 BIG = 0xFFFFFFFF
 MODES = {
     "default": None,
-    "lane": dict(t0=BIG, t1=BIG),
-    "wave": dict(t0=0, t1=BIG),
-    "group": dict(t0=0, t1=0),
+    "lane": dict(t0=BIG, t1=BIG, t_hub=BIG, tri=0),
+    "wave": dict(t0=0, t1=BIG, t_hub=BIG, tri=0),
+    "group": dict(t0=0, t1=0, t_hub=BIG, tri=0),
+    "hub": dict(t_hub=0, tri=0),
+    "tri": dict(tri=1),
+    "tri-lane": dict(t0=BIG, t1=BIG, t_hub=BIG, tri=1),
+    "tri-wave": dict(t0=0, t1=BIG, t_hub=BIG, tri=1),
+    "tri-group": dict(t0=0, t1=0, t_hub=BIG, tri=1),
+    "tri-hub": dict(t_hub=0, tri=1),
 }
 
 
@@ -63,10 +70,15 @@ def check(ctx, n, src, dst, want=None, modes=MODES, name=""):
         say(f"[gpu] {name} n={n} m={len(src)} mode={mode}")
         got, info = gpu_census(ctx, n, src, dst, mode)
         assert got.tolist() == want.tolist(), (name, mode, got.tolist(), want.tolist())
-        if mode != "default" and MODES[mode] and info["bucket_dyads"]:
-            idx = {"lane": 0, "wave": 1, "group": 2}[mode]
+        if mode in ("lane", "wave", "group", "hub") and info["bucket_dyads"]:
+            idx = {"lane": 0, "wave": 1, "group": 2, "hub": 3}[mode]
             total = sum(info["bucket_dyads"])
             assert info["bucket_dyads"][idx] == total, (mode, info["bucket_dyads"])
+        if mode.startswith("tri"):
+            assert info["fwd_entries"] == info["asym_dyads"] + info["mutual_dyads"], (mode, info)
+            if mode != "tri" and sum(info["tri_bucket_edges"]):
+                idx = {"tri-lane": 0, "tri-wave": 1, "tri-group": 2, "tri-hub": 3}[mode]
+                assert info["tri_bucket_edges"][idx] == sum(info["tri_bucket_edges"]), (mode, info)
     return want
 
 
@@ -310,7 +322,24 @@ def test_full_size_identities_and_sampled_ranges(ctx, which):
         for u0, u1 in _ranges_with_work(g0, 2e7, 3, rng):
             say(f"[gpu] range {which} [{u0},{u1})")
             assert ctx.census_range(g, u0, u1).tolist() == og.census_range(u0, u1).tolist()
+        # through the dyad records, with every dyad in the hub mode, and with none
+        default = ctx.get_tuning()
+        for t_hub in (0, BIG):
+            ctx.set_tuning(t_hub=t_hub, tri=0)
+            ctx.rebucket(g)
+            say(f"[gpu] {which} t_hub={t_hub} buckets={g.info['bucket_dyads']}")
+            assert ctx.census(g).tolist() == full.tolist()
+            u0, u1 = _ranges_with_work(g0, 2e7, 1, rng)[0]
+            assert ctx.census_range(g, u0, u1).tolist() == og.census_range(u0, u1).tolist()
+        # through the triangles of the forward lists, default and all-hub buckets
+        for t_hub in (BIG, 0):
+            ctx.set_tuning(**dict(default, t_hub=t_hub, tri=1))
+            ctx.rebucket(g)
+            say(f"[gpu] {which} tri t_hub={t_hub} edges={g.info['tri_bucket_edges']}")
+            assert ctx.census(g).tolist() == full.tolist()
+        ctx.set_tuning(**default)
     finally:
+        ctx.set_tuning(**default)
         g.release()
         og.close()
 

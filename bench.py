@@ -368,8 +368,9 @@ def main():
     #     8 B per task (the (u, v<<2|f) pair);
     #   hub mode: 4 B per streamed entry of the non-anchor rows, 4 B per staged
     #     anchor entry (once per task), 8 B per task;
-    #   totals pass (forward-list census): 8 B per dyad and 4 x 8 B of prefix
-    #     counts.
+    #   totals pass (forward-list census): per neighbour entry its word, its
+    #     row id and one prefix count (16 B), per row its bounds and the prefix
+    #     count at its end (16 B).
     tri = bool(ctx.get_tuning()["tri"]) and info["fwd_entries"] > 0
     if tri:
         cost, tasks = info["tri_bucket_cost"], info["tri_bucket_edges"]
@@ -384,7 +385,7 @@ def main():
                 (4.0 * cost[b] + 8.0 * tasks[b]) for name, b in kern}
     if tri:
         per_launch_ms["k_census_totals"] = ks["totals_ms"] / max(1, ks["totals_launches"])
-        bytes_of["k_census_totals"] = 40.0 * p_dyads
+        bytes_of["k_census_totals"] = 16.0 * 2 * p_dyads + 16.0 * g0.n
     dom_name = max(per_launch_ms, key=per_launch_ms.get)
     dom_ms = per_launch_ms[dom_name]
     bytes_dom = bytes_of[dom_name]

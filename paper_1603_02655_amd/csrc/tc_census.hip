@@ -28,7 +28,7 @@
 // single-graph kernels take the table as an argument: the 16-class table, or
 // for the labelled (64-class) census one of three pass tables that send the
 // codes whose (u, v) part is f to bin (code >> 2) and every other code to the
-// discard bin kDiscard, which is never flushed.
+// discard bin (index kNumClasses), which is never flushed.
 #include "tc_census.h"
 
 namespace tc {
@@ -37,8 +37,7 @@ namespace {
 
 __constant__ uint8_t c_table[64];
 
-constexpr int kBins = kNumClasses + 1;     // 16 classes and the discard bin
-constexpr uint32_t kDiscard = kNumClasses;
+constexpr int kBins = kNumClasses + 1;     // 16 classes and the discard bin (kNumClasses)
 
 // ---- class histograms in LDS ------------------------------------------------
 // lane_bins: one private row of bins per lane (no contention; used where every
@@ -211,22 +210,42 @@ __global__ __launch_bounds__(kLaneB) void k_census_lane(census_args L) {
     h.flush(L.acc);
 }
 
-// The per-dyad terms that need no intersection (the dyadic base and the
-// typed counts of N(u) above v and N(v) above u), one lane per dyad record:
-// with forward-list edge records the shared vertices come from the triangles.
-__global__ __launch_bounds__(kLaneB) void k_census_totals(census_args L) {
+// The per-dyad terms that need no intersection, for every dyad at once (the
+// forward-list path), one lane per neighbour entry: entry y of row x, with
+// the prefix counts of the direction bits, gives the typed counts of the
+// entries after y in row x.  When y > x these are the entries of N(u) above v
+// for the dyad (u, v) = (x, y); when y < x they are the entries of N(v) above
+// u for the dyad (y, x).  The dyadic base n - |N(u)| - |N(v)| is split the
+// same way: n - |N(x)| from the first side, -|N(x)| from the second.  Every
+// read is coalesced (the row of an entry is shared by its neighbours).
+__global__ __launch_bounds__(kLaneB) void k_census_totals(const uint32_t* __restrict__ nbr,
+                                                          const uint32_t* __restrict__ owner,
+                                                          const int64_t* __restrict__ row_ptr,
+                                                          const uint64_t* __restrict__ tpre, uint64_t U, uint64_t n,
+                                                          const uint8_t* __restrict__ table,
+                                                          unsigned long long* __restrict__ acc) {
     extern __shared__ unsigned long long lds[];
     __shared__ uint8_t T[64];
-    if (threadIdx.x < 64) T[threadIdx.x] = L.table[threadIdx.x];
+    if (threadIdx.x < 64) T[threadIdx.x] = table[threadIdx.x];
     lane_bins<kLaneB> h{lds};
     h.clear();
     __syncthreads();
-    for (uint64_t d = (uint64_t)blockIdx.x * kLaneB + threadIdx.x; d < L.count;
-         d += (uint64_t)gridDim.x * kLaneB) {
-        const dyad_rec r = load_rec(L.dyads + d);
-        add_totals(r, load_totals(r, L.tpre), L.n, T, h);
+    for (uint64_t e = (uint64_t)blockIdx.x * kLaneB + threadIdx.x; e < U; e += (uint64_t)gridDim.x * kLaneB) {
+        const uint32_t x = owner[e], ent = nbr[e];
+        const uint32_t y = ent >> 2, fxy = ent & 3u;
+        const uint64_t rb = (uint64_t)row_ptr[x], re = (uint64_t)row_ptr[x + 1];
+        const uint64_t pc = tpre[re] - tpre[e + 1];                 // direction bits after e in row x
+        const uint64_t tot = re - e - 1, out = pc & 0xffffffffull, in = pc >> 32;
+        const uint64_t mut = out + in - tot;
+        const bool first = y > x;                                   // x plays u, else v
+        const uint32_t f = first ? fxy : ((fxy & 1u) << 1) | (fxy >> 1);
+        const uint32_t sh = first ? 2u : 4u;
+        h.add(T[f], (unsigned long long)((first ? n : 0ull) - (re - rb)));
+        h.add(T[f | (1u << sh)], out - mut);
+        h.add(T[f | (2u << sh)], in - mut);
+        h.add(T[f | (3u << sh)], mut);
     }
-    h.flush(L.acc);
+    h.flush(acc);
 }
 
 // ---------------------------------------------------------- merge path ----
@@ -416,7 +435,7 @@ constexpr int kHubBucketBits = __builtin_ctz(kHubBuckets);
 static_assert((kHubBuckets & (kHubBuckets - 1)) == 0, "power-of-two bucket count");
 constexpr uint32_t kEmpty = 0xffffffffu;                 // never an entry (w < 2^23)
 constexpr uint32_t kHubGather = 8;
-constexpr uint32_t kHubFlushAfter = 1u << 26;             // probes per lane between bin flushes
+constexpr uint32_t kHubFlushAfter = 1u << 25;             // probes per lane between histogram flushes
 
 // First position in [lo, hi) of a sorted row whose vertex is >= w.
 __device__ inline uint32_t find_first_ge(const uint32_t* __restrict__ nbr, uint32_t lo, uint32_t hi, uint32_t w) {
@@ -488,19 +507,38 @@ __device__ inline void block_scan_u32(uint32_t* a, uint32_t count, uint32_t* wsu
     __syncthreads();
 }
 
-// LDS of the hub mode: the hash table, three per-dyad arrays, per-lane 32-bit
-// class bins for the shared vertices (the discard bin takes the misses and is never
-// read), and scan scratch.
+// What a shared vertex w of the dyad (or edge record) (u, v), u < v, adds to
+// the census depends only on the direction bits f = f_uv, fa = f_uw, fb = f_vw
+// (each 1, 2 or 3: the pairs are joined) and on where w lies: below u, between
+// u and v, or above v.  The hub mode counts shared vertices per such signature
+// (81 of them) in one 32-bit LDS histogram per wavefront and turns the counts
+// into class updates when it flushes.
+constexpr uint32_t kSigs = 81;
+
+__device__ inline uint32_t shared_sig(uint32_t w, uint32_t u, uint32_t v, uint32_t f, uint32_t fa, uint32_t fb) {
+    const uint32_t where = w > v ? 2u : (w > u ? 1u : 0u);
+    return (f - 1u) + 3u * (fa - 1u) + 9u * (fb - 1u) + 27u * where;
+}
+
+// Scales every update of one signature by its count.
+template <class H>
+struct scaled_bins {
+    H& h;
+    unsigned long long c;
+    __device__ inline void add(uint32_t cls, unsigned long long x) { h.add(cls, x * c); }
+};
+
+// LDS of the hub mode: the hash table, three per-dyad arrays, scan scratch and
+// the per-wavefront signature histograms.
 struct hub_lds {
     uint32_t* hash;   // kHubSlots, 16-byte aligned
     uint32_t* pos;    // next unprobed position in the other endpoint's row
     uint32_t* meta;   // (x << 3) | (anchor is u) << 2 | f_uv
     uint32_t* off;    // probes of this tile, then their exclusive scan (kHubChunk + 1)
-    uint32_t* bins;   // kBins x kHubB
     uint32_t* wsum;   // 4 words
-    uint32_t* cls;    // 64 packed class triples
+    uint32_t* sig;    // kSigs x (kHubB / 64)
 };
-constexpr uint32_t kHubLdsWords = kHubSlots + 2 * kHubChunk + (kHubChunk + 4) + kBins * kHubB + 4 + 64;
+constexpr uint32_t kHubLdsWords = kHubSlots + 2 * kHubChunk + (kHubChunk + 4) + 4 + kSigs * (kHubB / 64);
 
 __device__ inline hub_lds hub_carve(uint32_t* base) {
     uint32_t* p = base;
@@ -509,58 +547,40 @@ __device__ inline hub_lds hub_carve(uint32_t* base) {
     S.pos = p;   p += kHubChunk;
     S.meta = p;  p += kHubChunk;
     S.off = p;   p += kHubChunk + 4;
-    S.bins = p;  p += kBins * kHubB;
     S.wsum = p;  p += 4;
-    S.cls = p;
+    S.sig = p;
     return S;
 }
 
 __device__ inline void hub_bins_clear(const hub_lds& S) {
-    for (uint32_t k = threadIdx.x; k < kBins * kHubB; k += kHubB) S.bins[k] = 0;
+    for (uint32_t k = threadIdx.x; k < kSigs * (kHubB / 64); k += kHubB) S.sig[k] = 0;
 }
 
-// Adds the per-lane bins (signed 32-bit differences) to h: each wavefront
-// sums its lanes, lane 0 adds the sums.  Bins are left cleared.
-template <class H>
-__device__ inline void hub_bins_flush(const hub_lds& S, H& h) {
+// Adds the signature counts to h (one thread per wavefront and signature) and
+// clears them.
+template <bool Tri, class H>
+__device__ inline void hub_bins_flush(const hub_lds& S, const uint8_t* T, H& h) {
     __syncthreads();
-    const uint32_t lane = threadIdx.x & 63u;
-    for (uint32_t c = 0; c < kNumClasses; ++c) {
-        long long v = (long long)(int32_t)S.bins[c * kHubB + threadIdx.x];
-        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-        if (lane == 0 && v != 0) h.add(c, (unsigned long long)v);
-        S.bins[c * kHubB + threadIdx.x] = 0;
+    for (uint32_t k = threadIdx.x; k < kSigs * (kHubB / 64); k += kHubB) {
+        const uint32_t c = S.sig[k];
+        if (c == 0) continue;
+        S.sig[k] = 0;
+        const uint32_t s = k % kSigs;
+        const uint32_t f = 1u + s % 3u, fa = 1u + (s / 3u) % 3u, fb = 1u + (s / 9u) % 3u, where = s / 27u;
+        // ids that put w below u, between u and v, or above v
+        const uint32_t u = 1u, v = 3u, w = where * 2u;
+        scaled_bins<H> sh{h, (unsigned long long)c};
+        on_shared<Tri>(w, fa, fb, u, v, f, T, sh);
     }
     __syncthreads();
-}
-
-// Class lookup for a shared vertex, packed per (f_uv, f_a, f_b) with f_a the
-// direction bits of the pair (u, w) and f_b those of (v, w), one byte each:
-// T[f_uv | f_a << 2 | f_b << 4] (its full code), T[f_uv | f_a << 2] (the
-// u-only code it must not be counted under), T[f_uv | f_b << 4] (the v-only
-// code) and T[f_uv] (the dyadic code whose count grows by one).
-__device__ inline void hub_fill_cls(const hub_lds& S, const uint8_t* T) {
-    for (uint32_t k = threadIdx.x; k < 64; k += blockDim.x) {
-        const uint32_t f = k & 3u, fa = (k >> 2) & 3u, fb = k >> 4;
-        S.cls[k] = (uint32_t)T[k] | ((uint32_t)T[f | (fa << 2)] << 8) | ((uint32_t)T[f | (fb << 4)] << 16) |
-                   ((uint32_t)T[f] << 24);
-    }
 }
 
 // One hub task on the whole workgroup (kHubB threads).  Per tile of the
 // anchor row: clear and fill the hash table; count, for every dyad, the
 // entries of the other row that fall in the tile's vertex range; scan the
 // counts; then every lane probes an equal contiguous slice of the flattened
-// (dyad, entry) list with kHubGather gathers in flight.  The shared-vertex
-// bookkeeping is branch-free: every probe adds to four lane-private bins
-// (misses to the discard bin).
-// 32-bit lane-private bins of the hub mode as a histogram (a triangle's
-// updates; each changes a bin by one).
-struct hub_lane_bins {
-    uint32_t* my;
-    __device__ inline void add(uint32_t cls, unsigned long long x) { atomicAdd(&my[cls * kHubB], (uint32_t)x); }
-};
-
+// (dyad, entry) list with kHubGather gathers in flight.  A hit adds one to its
+// wavefront's count of the hit's signature.
 template <bool Tri, class H>
 __device__ inline void hub_task_run(const hub_task& tk, const dyad_rec* __restrict__ dyads,
                                     const uint32_t* __restrict__ nbr, const uint64_t* __restrict__ tpre, uint64_t n,
@@ -568,7 +588,7 @@ __device__ inline void hub_task_run(const hub_task& tk, const dyad_rec* __restri
                                     uint32_t& since) {
     const uint32_t tid = threadIdx.x;
     const uint32_t nrec = tk.end - tk.begin, a = tk.anchor;
-    uint32_t* my_bins = S.bins + tid;
+    uint32_t* my_sig = S.sig + (tid >> 6) * kSigs;
     const dyad_rec r0 = load_rec(dyads + tk.begin);
     const uint32_t hb = r0.u == a ? r0.bu : r0.bv, he = r0.u == a ? r0.eu : r0.ev;
     const bool multi_tile = he - hb > kHubTile;
@@ -643,34 +663,18 @@ __device__ inline void hub_task_run(const hub_task& tk, const dyad_rec* __restri
                     const uint32_t u = anchor_u ? a : x, v = anchor_u ? x : a, w = e[k] >> 2;
                     const uint32_t fx = e[k] & 3u, fh = hit & 3u;
                     const uint32_t fa = anchor_u ? fh : fx, fb = anchor_u ? fx : fh;
-                    if constexpr (Tri) {
-                        if (!miss) {
-                            hub_lane_bins lb{my_bins};
-                            on_triangle(w, fa, fb, u, v, fuv, T, lb);
-                        }
-                    } else {
-                        const bool gv = !miss && w > v, gu = !miss && w > u;
-                        const uint32_t c3 = S.cls[fuv | (fa << 2) | (fb << 4)];
-                        const uint32_t b0 = miss ? kDiscard : c3 >> 24;
-                        const uint32_t b1 = gv ? c3 & 255u : kDiscard;
-                        const uint32_t b2 = gv ? (c3 >> 8) & 255u : kDiscard;
-                        const uint32_t b3 = gu ? (c3 >> 16) & 255u : kDiscard;
-                        atomicAdd(&my_bins[b0 * kHubB], 1u);
-                        atomicAdd(&my_bins[b1 * kHubB], 1u);
-                        atomicAdd(&my_bins[b2 * kHubB], 0xffffffffu);
-                        atomicAdd(&my_bins[b3 * kHubB], 0xffffffffu);
-                    }
+                    if (!miss) atomicAdd(&my_sig[shared_sig(w, u, v, fuv, fa, fb)], 1u);
                 }
             }
         }
         __syncthreads();
         if (multi_tile)
             for (uint32_t i = tid; i < nrec; i += kHubB) S.pos[i] += S.off[i + 1] - S.off[i];
-        // A lane's 32-bit bins change by at most one per probe: flush them long
-        // before 2^31 probes (`per` is the same on every lane of the workgroup).
+        // A wavefront's 32-bit signature counts grow by at most 64 per probe
+        // step: flush them long before 2^32 (`per` is the same on every lane).
         since += per;
         if (since >= kHubFlushAfter) {
-            hub_bins_flush(S, h);
+            hub_bins_flush<Tri>(S, T, h);
             since = 0;
         }
         __syncthreads();
@@ -690,7 +694,6 @@ __global__ __launch_bounds__(kHubB) void k_census_hub(census_args L, const hub_t
     const hub_lds S = hub_carve(hub_words);
     hub_bins_clear(S);
     __syncthreads();
-    hub_fill_cls(S, T);
     uint32_t since = 0;
     const uint32_t xcd = blockIdx.x % kXcds;
     if (threadIdx.x == 0) s_next = take_chunk(ctr, xcd);
@@ -704,7 +707,7 @@ __global__ __launch_bounds__(kHubB) void k_census_hub(census_args L, const hub_t
         t = s_next;
         __syncthreads();
     }
-    hub_bins_flush(S, h);
+    hub_bins_flush<Tri>(S, T, h);
     h.flush(L.acc);
 }
 
@@ -779,13 +782,12 @@ __global__ __launch_bounds__(kBatchB) void k_census_batch(const graph_desc* __re
         } else {
             const hub_lds S = hub_carve(tiles);
             hub_bins_clear(S);
-            hub_fill_cls(S, T);
             uint32_t since = 0;
             for (uint32_t k = it.begin; k < it.end; ++k) {
                 hub_task_run<false>(g.hub_tasks[k], g.dyads, g.nbr, g.tpre, g.n, 0u, 0xffffffffu, S, T, h, since);
                 __syncthreads();
             }
-            hub_bins_flush(S, h);
+            hub_bins_flush<false>(S, T, h);
         }
         __syncthreads();
         idx = s_next;
@@ -861,11 +863,11 @@ hipError_t census_launch(const device_graph& g, const census_slices& sl, bool tr
     const uint32_t ntasks = tri ? g.tri.edges.n_tasks : g.n_hub_tasks;
     if (tri) {
         if (ev) (void)hipEventRecord(ev[2 * kBuckets], s);
-        if (g.p > 0) {
-            census_args L{g.dyads, (uint32_t)g.p, g.nbr, g.tpre, (uint64_t)g.n, acc, 0u, 0xffffffffu, table};
-            uint32_t grid = (uint32_t)std::min<uint64_t>((g.p + kLaneB - 1) / kLaneB, cfg.lane_blocks);
+        if (g.U > 0) {
+            uint32_t grid = (uint32_t)std::min<uint64_t>((g.U + kLaneB - 1) / kLaneB, cfg.lane_blocks);
             size_t sh = sizeof(unsigned long long) * lane_bins<kLaneB>::kWords;
-            hipLaunchKernelGGL(k_census_totals, dim3(grid), dim3(kLaneB), sh, s, L);
+            hipLaunchKernelGGL(k_census_totals, dim3(grid), dim3(kLaneB), sh, s, g.nbr, g.owner, g.row_ptr, g.tpre,
+                               g.U, (uint64_t)g.n, table, acc);
         }
         if (ev) (void)hipEventRecord(ev[2 * kBuckets + 1], s);
     }

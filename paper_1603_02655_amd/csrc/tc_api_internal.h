@@ -72,7 +72,7 @@ inline tc_tuning default_tuning(int cu_count) {
     int cu = cu_count > 0 ? cu_count : 256;
     t.t0 = 64;      // lane mode for k < 64
     t.t1 = 4096;    // wave mode for 64 <= k < 4096, group mode above
-    t.t_hub = 64;   // records with a row of length >= 64: hub mode
+    t.t_hub = 32;   // records with a row of length >= 32: hub mode
     t.lane_blocks = (uint32_t)cu * 8;
     t.wave_blocks = (uint32_t)cu * 10;
     t.group_blocks = (uint32_t)cu * 2;

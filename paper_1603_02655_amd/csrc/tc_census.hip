@@ -173,24 +173,53 @@ constexpr uint32_t kSentinel = 0xffffffffu;
 // memory (L1/L2 resident for the short rows of this bucket).
 constexpr int kLaneB = 256;
 
+// The two rows are compared kLaneChunk entries at a time: a chunk of each is
+// loaded with independent loads and every pair of the two chunks compared in
+// registers; then the chunk whose last vertex is smaller is replaced.  No pair
+// is compared twice and no shared vertex is missed: the chunk left in place
+// holds no vertex below the last one of the chunk that is replaced, and the
+// next chunk of a row starts above its current one.
+constexpr uint32_t kLaneChunk = 8;
+
+__device__ inline void load_chunk(const uint32_t* __restrict__ nbr, uint32_t pos, uint32_t end, uint32_t pad,
+                                  uint32_t (&c)[kLaneChunk]) {
+#pragma unroll
+    for (uint32_t k = 0; k < kLaneChunk; ++k) c[k] = pos + k < end ? nbr[pos + k] : pad;
+}
+
 template <bool Tri, class H>
 __device__ inline void lane_dyad(const dyad_rec& r, const uint32_t* __restrict__ nbr, const uint64_t* __restrict__ tpre,
                                  uint64_t n, const uint8_t* T, H& h) {
     dyad_totals t{};
     if constexpr (!Tri) t = load_totals(r, tpre);
     const uint32_t u = r.u, v = r.vf >> 2, f = r.vf & 3u;
+    // pads: never equal to an entry or to each other (entries are below 2^25)
+    constexpr uint32_t kPadA = 0xffffffffu, kPadB = 0xfffffff0u;
     uint32_t i = r.bu, j = r.bv;
-    // rows are never empty: v is in row u and u is in row v (dyad records);
-    // edge records with an empty forward list are never emitted
-    uint32_t a = nbr[i], b = nbr[j];
+    uint32_t A[kLaneChunk], B[kLaneChunk];
+    load_chunk(nbr, i, r.eu, kPadA, A);
+    load_chunk(nbr, j, r.ev, kPadB, B);
     for (;;) {
-        if ((a ^ b) < 4u) on_shared<Tri>(a >> 2, a & 3u, b & 3u, u, v, f, T, h);
-        if (a <= (b | 3u)) {
-            if (++i >= r.eu) break;
-            a = nbr[i];
+#pragma unroll
+        for (uint32_t p = 0; p < kLaneChunk; ++p)
+#pragma unroll
+            for (uint32_t q = 0; q < kLaneChunk; ++q)
+                if ((A[p] ^ B[q]) < 4u) on_shared<Tri>(A[p] >> 2, A[p] & 3u, B[q] & 3u, u, v, f, T, h);
+        const uint32_t la = min(kLaneChunk, r.eu - i), lb = min(kLaneChunk, r.ev - j);
+        uint32_t lastA = A[0], lastB = B[0];
+#pragma unroll
+        for (uint32_t k = 1; k < kLaneChunk; ++k) {
+            lastA = k < la ? A[k] : lastA;
+            lastB = k < lb ? B[k] : lastB;
+        }
+        if (lastA <= (lastB | 3u)) {
+            i += kLaneChunk;
+            if (i >= r.eu) break;
+            load_chunk(nbr, i, r.eu, kPadA, A);
         } else {
-            if (++j >= r.ev) break;
-            b = nbr[j];
+            j += kLaneChunk;
+            if (j >= r.ev) break;
+            load_chunk(nbr, j, r.ev, kPadB, B);
         }
     }
     if constexpr (!Tri) add_totals(r, t, n, T, h);
@@ -230,20 +259,40 @@ __global__ __launch_bounds__(kLaneB) void k_census_totals(const uint32_t* __rest
     lane_bins<kLaneB> h{lds};
     h.clear();
     __syncthreads();
-    for (uint64_t e = (uint64_t)blockIdx.x * kLaneB + threadIdx.x; e < U; e += (uint64_t)gridDim.x * kLaneB) {
-        const uint32_t x = owner[e], ent = nbr[e];
-        const uint32_t y = ent >> 2, fxy = ent & 3u;
-        const uint64_t rb = (uint64_t)row_ptr[x], re = (uint64_t)row_ptr[x + 1];
-        const uint64_t pc = tpre[re] - tpre[e + 1];                 // direction bits after e in row x
-        const uint64_t tot = re - e - 1, out = pc & 0xffffffffull, in = pc >> 32;
-        const uint64_t mut = out + in - tot;
-        const bool first = y > x;                                   // x plays u, else v
-        const uint32_t f = first ? fxy : ((fxy & 1u) << 1) | (fxy >> 1);
-        const uint32_t sh = first ? 2u : 4u;
-        h.add(T[f], (unsigned long long)((first ? n : 0ull) - (re - rb)));
-        h.add(T[f | (1u << sh)], out - mut);
-        h.add(T[f | (2u << sh)], in - mut);
-        h.add(T[f | (3u << sh)], mut);
+    constexpr uint32_t kPer = 4;   // entries per thread and step, loaded together
+    for (uint64_t base = (uint64_t)blockIdx.x * kLaneB * kPer; base < U; base += (uint64_t)gridDim.x * kLaneB * kPer) {
+        uint32_t x[kPer], ent[kPer];
+        uint64_t rb[kPer], re[kPer], pend[kPer], pnext[kPer];
+#pragma unroll
+        for (uint32_t k = 0; k < kPer; ++k) {
+            const uint64_t e = base + k * kLaneB + threadIdx.x;
+            x[k] = e < U ? owner[e] : 0u;
+            ent[k] = e < U ? nbr[e] : 0u;
+            pnext[k] = e < U ? tpre[e + 1] : 0ull;
+        }
+#pragma unroll
+        for (uint32_t k = 0; k < kPer; ++k) {
+            rb[k] = (uint64_t)row_ptr[x[k]];
+            re[k] = (uint64_t)row_ptr[x[k] + 1];
+        }
+#pragma unroll
+        for (uint32_t k = 0; k < kPer; ++k) pend[k] = tpre[re[k]];
+#pragma unroll
+        for (uint32_t k = 0; k < kPer; ++k) {
+            const uint64_t e = base + k * kLaneB + threadIdx.x;
+            if (e >= U) continue;
+            const uint32_t y = ent[k] >> 2, fxy = ent[k] & 3u;
+            const uint64_t pc = pend[k] - pnext[k];                 // direction bits after e in row x
+            const uint64_t tot = re[k] - e - 1, out = pc & 0xffffffffull, in = pc >> 32;
+            const uint64_t mut = out + in - tot;
+            const bool first = y > x[k];                            // x plays u, else v
+            const uint32_t f = first ? fxy : ((fxy & 1u) << 1) | (fxy >> 1);
+            const uint32_t sh = first ? 2u : 4u;
+            h.add(T[f], (unsigned long long)((first ? n : 0ull) - (re[k] - rb[k])));
+            h.add(T[f | (1u << sh)], out - mut);
+            h.add(T[f | (2u << sh)], in - mut);
+            h.add(T[f | (3u << sh)], mut);
+        }
     }
     h.flush(acc);
 }
@@ -864,7 +913,7 @@ hipError_t census_launch(const device_graph& g, const census_slices& sl, bool tr
     if (tri) {
         if (ev) (void)hipEventRecord(ev[2 * kBuckets], s);
         if (g.U > 0) {
-            uint32_t grid = (uint32_t)std::min<uint64_t>((g.U + kLaneB - 1) / kLaneB, cfg.lane_blocks);
+            uint32_t grid = (uint32_t)std::min<uint64_t>((g.U + 4 * kLaneB - 1) / (4 * kLaneB), cfg.lane_blocks);
             size_t sh = sizeof(unsigned long long) * lane_bins<kLaneB>::kWords;
             hipLaunchKernelGGL(k_census_totals, dim3(grid), dim3(kLaneB), sh, s, g.nbr, g.owner, g.row_ptr, g.tpre,
                                g.U, (uint64_t)g.n, table, acc);

@@ -627,9 +627,9 @@ __device__ inline void hub_bins_flush(const hub_lds& S, const uint8_t* T, H& h) 
 // One hub task on the whole workgroup (kHubB threads).  Per tile of the
 // anchor row: clear and fill the hash table; count, for every dyad, the
 // entries of the other row that fall in the tile's vertex range; scan the
-// counts; then every lane probes an equal contiguous slice of the flattened
-// (dyad, entry) list with kHubGather gathers in flight.  A hit adds one to its
-// wavefront's count of the hit's signature.
+// counts; then each wavefront probes a quarter of the flattened (dyad, entry)
+// list, 64 adjacent entries per gather and kHubGather gathers in flight.  A hit
+// adds one to its wavefront's count of the hit's signature.
 template <bool Tri, class H>
 __device__ inline void hub_task_run(const hub_task& tk, const dyad_rec* __restrict__ dyads,
                                     const uint32_t* __restrict__ nbr, const uint64_t* __restrict__ tpre, uint64_t n,
@@ -673,24 +673,31 @@ __device__ inline void hub_task_run(const hub_task& tk, const dyad_rec* __restri
         __syncthreads();
         block_scan_u32(S.off, nrec, S.wsum);
         const uint32_t P = S.off[nrec];
-        const uint32_t per = (P + kHubB - 1) / kHubB;
-        const uint32_t f0 = min(P, tid * per), f1 = min(P, f0 + per);
-        if (f0 < f1) {
-            uint32_t lo = 0, hi = nrec;                 // record holding f0: off[i] <= f0 < off[i+1]
+        // Wavefront w takes the w-th quarter [q0, q1) of the flattened list and
+        // walks it in windows of 64 consecutive entries, so every gather reads
+        // 64 adjacent words; a lane keeps the record of its current entry and
+        // moves it forward as the windows pass record boundaries.
+        const uint32_t lane = tid & 63u, wid = tid >> 6;
+        constexpr uint32_t kWaves = kHubB / 64;
+        const uint32_t q0 = (uint32_t)(((uint64_t)P * wid) / kWaves), q1 = (uint32_t)(((uint64_t)P * (wid + 1)) / kWaves);
+        const uint32_t per = (P + kHubB - 1) / kHubB + 1;   // bound on a lane's probes in this tile
+        const uint32_t first = q0 + lane;
+        if (first < q1) {
+            uint32_t lo = 0, hi = nrec;                 // record holding `first`: off[i] <= first < off[i+1]
             while (hi - lo > 1) {
                 const uint32_t mid = (lo + hi) >> 1;
-                if (S.off[mid] <= f0) lo = mid; else hi = mid;
+                if (S.off[mid] <= first) lo = mid; else hi = mid;
             }
             uint32_t i = lo;
             uint32_t next = S.off[i + 1], base = S.pos[i] - S.off[i], m = S.meta[i];
-            for (uint32_t f = f0; f < f1; f += kHubGather) {
+            for (uint32_t f = first; f < q1; f += 64u * kHubGather) {
                 uint32_t e[kHubGather], mk[kHubGather];
 #pragma unroll
                 for (uint32_t k = 0; k < kHubGather; ++k) {
-                    const uint32_t ff = f + k;
+                    const uint32_t ff = f + 64u * k;
                     e[k] = kEmpty;
                     mk[k] = m;
-                    if (ff < f1) {
+                    if (ff < q1) {
                         if (ff >= next) {
                             do {
                                 ++i;

@@ -738,7 +738,7 @@ __device__ inline void hub_task_run(const hub_task& tk, const dyad_rec* __restri
 }
 
 template <bool Tri>
-__global__ __launch_bounds__(kHubB) void k_census_hub(census_args L, const hub_task* __restrict__ tasks,
+__global__ __launch_bounds__(kHubB) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_census_hub(census_args L, const hub_task* __restrict__ tasks,
                                                       uint32_t ntasks, unsigned int* ctr) {
     __shared__ __attribute__((aligned(16))) uint32_t hub_words[kHubLdsWords];
     __shared__ unsigned long long bins[wave_bins<kHubB>::kWords];

@@ -39,8 +39,8 @@ static_assert(sizeof(dyad_rec) == 32, "dyad record is two 16-byte loads");
 struct hub_task {
     uint32_t begin, end, anchor, pad;
 };
-constexpr uint32_t kHubChunk = 1024;          // records per hub task
-constexpr uint32_t kHubTileEntries = 2048;    // anchor-row entries staged per LDS tile
+constexpr uint32_t kHubChunk = 512;           // records per hub task
+constexpr uint32_t kHubTileEntries = 1024;    // anchor-row entries staged per LDS tile
 
 // Bucket thresholds.  Dyads with max(|N(u)|, |N(v)|) >= t_hub go to the hub
 // bucket (anchored at the larger-degree endpoint, ties to the larger id); the

@@ -60,6 +60,24 @@ def generate_pool(fn, count):
         return list(ex.map(fn, range(count), chunksize=max(1, count // (4 * workers))))
 
 
+def census_bytes(info: dict, n: int, tri: bool) -> float:
+    """Algorithmic bytes of one whole census of a graph by the per-kernel
+    models (see the roofline comment in main): merge modes 4 B per merged entry
+    + 8 B per record, hub mode 4 B per streamed and staged entry + 8 B per
+    record, and on the forward-list path the totals pass's 16 B per neighbour
+    entry + 16 B per row."""
+    if tri:
+        cost, recs = info["tri_bucket_cost"], info["tri_bucket_edges"]
+        stream, staged = info["tri_stream"], info["tri_staged"]
+        p = info["asym_dyads"] + info["mutual_dyads"]
+        base = 16.0 * 2 * p + 16.0 * n
+    else:
+        cost, recs = info["bucket_cost"], info["bucket_dyads"]
+        stream, staged = info["hub_stream"], info["hub_staged"]
+        base = 0.0
+    return (base + 4.0 * sum(cost[:3]) + 8.0 * sum(recs[:3]) + 4.0 * (stream + staged) + 8.0 * recs[3])
+
+
 def bench_batch(args):
     """Batched census of a pool of uneven R-MAT graphs: one persistent launch
     (captured HIP graph, autotuned thresholds) against one launch sequence per
@@ -100,10 +118,9 @@ def bench_batch(args):
     ctx.set_timing(False)
     assert out.tolist() == each.tolist()
     step_s = el / args.steps
-    sum_cost = sum(sum(h.info["bucket_cost"]) for h in hs)
-    dyads = sum(sum(h.info["bucket_dyads"]) for h in hs)
     launch_ms = ks["batch_ms"] / max(1, ks["batch_launches"])
-    bytes_alg = 4.0 * sum_cost + 8.0 * dyads
+    tri = bool(ctx.get_tuning()["tri"])
+    bytes_alg = sum(census_bytes(h.info, h.n, tri and h.info["fwd_entries"] > 0) for h in hs)
     achieved = bytes_alg / (launch_ms / 1000.0) / 1e9 if launch_ms > 0 else 0.0
     line = {
         "metric": "census arcs/sec (batched)", "value": arcs / step_s, "unit": "arcs/s", "n_gpus": 1,
@@ -118,7 +135,8 @@ def bench_batch(args):
         "speedup_vs_per_graph": each_s / step_s,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_census_batch",
-                     "kernel_ms": launch_ms},
+                     "kernel_ms": launch_ms, "bytes_per_launch": bytes_alg},
+        "path": "forward-list triangles" if tri else "dyad intersections",
         "autotune_s": tune_s,
     }
     for h in hs:

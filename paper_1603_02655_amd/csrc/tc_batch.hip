@@ -25,6 +25,7 @@ struct batch_plan {
     hipGraphExec_t exec = nullptr;
     uint32_t grid = 0;
     bool valid = false;                     // buffers describe `graphs`
+    bool tri = false;                       // ... through their forward lists
 
     void release() {
         if (exec) (void)hipGraphExecDestroy(exec);
@@ -56,18 +57,45 @@ void batch_forget_graph_locked(tc_context_s* ctx, tc_graph g) {
     }
 }
 
-// Work items of one graph: hub tasks and group-mode dyads first (largest),
-// then wave-mode chunks, then lane-mode chunks.
-void append_items(const device_graph& g, uint32_t gi, std::vector<work_item>& out) {
-    for (uint32_t t = 0; t < g.n_hub_tasks; ++t) out.push_back(work_item{gi, kItemHub, t, t + 1});
-    for (uint64_t d = g.bucket_off[2]; d < g.bucket_off[3]; ++d)
-        out.push_back(work_item{gi, kItemGroup, (uint32_t)d, (uint32_t)d + 1});
-    for (uint64_t d = g.bucket_off[1]; d < g.bucket_off[2]; d += kBatchWavePerItem)
-        out.push_back(work_item{gi, kItemWave, (uint32_t)d,
-                                (uint32_t)std::min<uint64_t>(d + kBatchWavePerItem, g.bucket_off[2])});
-    for (uint64_t d = g.bucket_off[0]; d < g.bucket_off[1]; d += kBatchLanePerItem)
-        out.push_back(work_item{gi, kItemLane, (uint32_t)d,
-                                (uint32_t)std::min<uint64_t>(d + kBatchLanePerItem, g.bucket_off[1])});
+graph_desc describe(const device_graph& g) {
+    graph_desc d{};
+    d.dyads = g.dyads;
+    d.nbr = g.nbr;
+    d.tpre = g.tpre;
+    d.n = (uint64_t)g.n;
+    d.hub_tasks = g.hub_tasks;
+    d.owner = g.owner;
+    d.row_ptr = g.row_ptr;
+    d.U = g.U;
+    d.edges = g.tri.edges.recs;
+    d.fwd = g.tri.fwd;
+    d.edge_tasks = g.tri.edges.tasks;
+    return d;
+}
+
+// Work items of one graph: hub tasks and group-mode records first (largest),
+// then wave-mode chunks, then lane-mode chunks; over the forward-list edge
+// records (after the totals chunks) when `tri`.
+void append_items(const device_graph& g, uint32_t gi, bool tri, std::vector<work_item>& out) {
+    const uint64_t* off = g.bucket_off;
+    uint32_t ntasks = g.n_hub_tasks, flag = 0;
+    if (tri) {
+        for (uint64_t e = 0; e < g.U; e += kBatchTotalsPerItem)
+            out.push_back(work_item{gi, kItemTotals, (uint32_t)e,
+                                    (uint32_t)std::min<uint64_t>(e + kBatchTotalsPerItem, g.U)});
+        off = g.tri.edges.off;
+        ntasks = g.tri.edges.n_tasks;
+        flag = kItemTri;
+    }
+    for (uint32_t t = 0; t < ntasks; ++t) out.push_back(work_item{gi, kItemHub | flag, t, t + 1});
+    for (uint64_t d = off[2]; d < off[3]; ++d)
+        out.push_back(work_item{gi, kItemGroup | flag, (uint32_t)d, (uint32_t)d + 1});
+    for (uint64_t d = off[1]; d < off[2]; d += kBatchWavePerItem)
+        out.push_back(work_item{gi, kItemWave | flag, (uint32_t)d,
+                                (uint32_t)std::min<uint64_t>(d + kBatchWavePerItem, off[2])});
+    for (uint64_t d = off[0]; d < off[1]; d += kBatchLanePerItem)
+        out.push_back(work_item{gi, kItemLane | flag, (uint32_t)d,
+                                (uint32_t)std::min<uint64_t>(d + kBatchLanePerItem, off[1])});
 }
 
 namespace {
@@ -123,13 +151,14 @@ extern "C" int tc_census_batch(tc_context ctx, const tc_graph* graphs, int32_t c
     batch_plan* p = ctx->batch;
     std::vector<tc_graph> want(graphs, graphs + count);
     hipError_t e = hipSuccess;
-    if (!(p->valid && p->graphs == want && p->grid == ctx->tuning.batch_blocks)) {
+    const bool tri = ctx->tuning.tri != 0;
+    if (!(p->valid && p->graphs == want && p->grid == ctx->tuning.batch_blocks && p->tri == tri)) {
         std::vector<work_item> items;
         std::vector<graph_desc> descs(count);
         for (int32_t i = 0; i < count; ++i) {
             const device_graph& g = graphs[i]->g;
-            descs[i] = graph_desc{g.dyads, g.nbr, g.tpre, (uint64_t)g.n, g.hub_tasks, 0};
-            append_items(g, (uint32_t)i, items);
+            descs[i] = describe(g);
+            append_items(g, (uint32_t)i, tri && g.tri.fwd_ptr, items);
         }
         e = ensure_capacity(p, (uint32_t)count, (uint32_t)items.size(), ctx->stream, ctx->tuning.batch_blocks);
         if (e != hipSuccess) return status_from_hip(e);
@@ -147,6 +176,7 @@ extern "C" int tc_census_batch(tc_context ctx, const tc_graph* graphs, int32_t c
         }
         p->graphs = want;
         p->valid = true;
+        p->tri = tri;
     }
     if (ctx->timing) (void)hipEventRecord(ctx->ev[0], ctx->stream);
     e = hipGraphLaunch(p->exec, ctx->stream);

@@ -21,18 +21,28 @@ struct census_slices {
 
 // ---- batched launch over many graphs ----
 struct graph_desc {
-    const dyad_rec* dyads;
+    const dyad_rec* dyads;       // dyad records
     const uint32_t* nbr;
     const uint64_t* tpre;
     uint64_t n;
     const hub_task* hub_tasks;
+    const uint32_t* owner;
+    const int64_t* row_ptr;
+    uint64_t U;                  // neighbour entries
+    const dyad_rec* edges;       // forward-list edge records (null without forward lists)
+    const uint32_t* fwd;
+    const hub_task* edge_tasks;
     uint64_t pad;
 };
-enum : uint32_t { kItemLane = 0, kItemWave = 1, kItemGroup = 2, kItemHub = 3 };
+// Item kinds: the mode (lane / wave / group / hub), with kItemTri when the item
+// indexes the forward-list edge records; kItemTotals covers neighbour entries
+// [begin, end) of the totals pass.
+enum : uint32_t { kItemLane = 0, kItemWave = 1, kItemGroup = 2, kItemHub = 3, kItemTri = 4, kItemTotals = 8 };
 struct work_item {
-    uint32_t graph, kind, begin, end;   // dyads [begin, end) of graph `graph`'s record array;
+    uint32_t graph, kind, begin, end;   // records [begin, end) of graph `graph`'s record array;
                                         // hub items: hub tasks [begin, end) of the graph
 };
+constexpr uint32_t kBatchTotalsPerItem = 1024;   // neighbour entries per totals item
 constexpr uint32_t kBatchLanePerItem = 256;   // one dyad per thread of a 256-thread workgroup
 constexpr uint32_t kBatchWavePerItem = 16;    // four wavefronts, four dyads each
 

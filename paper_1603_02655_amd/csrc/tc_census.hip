@@ -247,6 +247,48 @@ __global__ __launch_bounds__(kLaneB) void k_census_lane(census_args L) {
 // u for the dyad (y, x).  The dyadic base n - |N(u)| - |N(v)| is split the
 // same way: n - |N(x)| from the first side, -|N(x)| from the second.  Every
 // read is coalesced (the row of an entry is shared by its neighbours).
+// Entries base + k * B + threadIdx.x (k < kPer) below `end`, their loads
+// issued before any is used.
+template <uint32_t kPer, uint32_t B, class H>
+__device__ inline void totals_entries(uint64_t base, uint64_t end, const uint32_t* __restrict__ nbr,
+                                      const uint32_t* __restrict__ owner, const int64_t* __restrict__ row_ptr,
+                                      const uint64_t* __restrict__ tpre, uint64_t n, const uint8_t* T, H& h) {
+    uint32_t x[kPer], ent[kPer];
+    uint64_t rb[kPer], re[kPer], pend[kPer], pnext[kPer];
+#pragma unroll
+    for (uint32_t k = 0; k < kPer; ++k) {
+        const uint64_t e = base + k * B + threadIdx.x;
+        x[k] = e < end ? owner[e] : 0u;
+        ent[k] = e < end ? nbr[e] : 0u;
+        pnext[k] = e < end ? tpre[e + 1] : 0ull;
+    }
+#pragma unroll
+    for (uint32_t k = 0; k < kPer; ++k) {
+        rb[k] = (uint64_t)row_ptr[x[k]];
+        re[k] = (uint64_t)row_ptr[x[k] + 1];
+    }
+#pragma unroll
+    for (uint32_t k = 0; k < kPer; ++k) pend[k] = tpre[re[k]];
+#pragma unroll
+    for (uint32_t k = 0; k < kPer; ++k) {
+        const uint64_t e = base + k * B + threadIdx.x;
+        if (e >= end) continue;
+        const uint32_t y = ent[k] >> 2, fxy = ent[k] & 3u;
+        const uint64_t pc = pend[k] - pnext[k];                 // direction bits after e in row x
+        const uint64_t tot = re[k] - e - 1, out = pc & 0xffffffffull, in = pc >> 32;
+        const uint64_t mut = out + in - tot;
+        const bool first = y > x[k];                            // x plays u, else v
+        const uint32_t f = first ? fxy : swap_dir(fxy);
+        const uint32_t sh = first ? 2u : 4u;
+        h.add(T[f], (unsigned long long)((first ? n : 0ull) - (re[k] - rb[k])));
+        h.add(T[f | (1u << sh)], out - mut);
+        h.add(T[f | (2u << sh)], in - mut);
+        h.add(T[f | (3u << sh)], mut);
+    }
+}
+
+constexpr uint32_t kTotalsPer = 4;   // entries per thread and step
+
 __global__ __launch_bounds__(kLaneB) void k_census_totals(const uint32_t* __restrict__ nbr,
                                                           const uint32_t* __restrict__ owner,
                                                           const int64_t* __restrict__ row_ptr,
@@ -259,41 +301,9 @@ __global__ __launch_bounds__(kLaneB) void k_census_totals(const uint32_t* __rest
     lane_bins<kLaneB> h{lds};
     h.clear();
     __syncthreads();
-    constexpr uint32_t kPer = 4;   // entries per thread and step, loaded together
-    for (uint64_t base = (uint64_t)blockIdx.x * kLaneB * kPer; base < U; base += (uint64_t)gridDim.x * kLaneB * kPer) {
-        uint32_t x[kPer], ent[kPer];
-        uint64_t rb[kPer], re[kPer], pend[kPer], pnext[kPer];
-#pragma unroll
-        for (uint32_t k = 0; k < kPer; ++k) {
-            const uint64_t e = base + k * kLaneB + threadIdx.x;
-            x[k] = e < U ? owner[e] : 0u;
-            ent[k] = e < U ? nbr[e] : 0u;
-            pnext[k] = e < U ? tpre[e + 1] : 0ull;
-        }
-#pragma unroll
-        for (uint32_t k = 0; k < kPer; ++k) {
-            rb[k] = (uint64_t)row_ptr[x[k]];
-            re[k] = (uint64_t)row_ptr[x[k] + 1];
-        }
-#pragma unroll
-        for (uint32_t k = 0; k < kPer; ++k) pend[k] = tpre[re[k]];
-#pragma unroll
-        for (uint32_t k = 0; k < kPer; ++k) {
-            const uint64_t e = base + k * kLaneB + threadIdx.x;
-            if (e >= U) continue;
-            const uint32_t y = ent[k] >> 2, fxy = ent[k] & 3u;
-            const uint64_t pc = pend[k] - pnext[k];                 // direction bits after e in row x
-            const uint64_t tot = re[k] - e - 1, out = pc & 0xffffffffull, in = pc >> 32;
-            const uint64_t mut = out + in - tot;
-            const bool first = y > x[k];                            // x plays u, else v
-            const uint32_t f = first ? fxy : ((fxy & 1u) << 1) | (fxy >> 1);
-            const uint32_t sh = first ? 2u : 4u;
-            h.add(T[f], (unsigned long long)((first ? n : 0ull) - (re[k] - rb[k])));
-            h.add(T[f | (1u << sh)], out - mut);
-            h.add(T[f | (2u << sh)], in - mut);
-            h.add(T[f | (3u << sh)], mut);
-        }
-    }
+    for (uint64_t base = (uint64_t)blockIdx.x * kLaneB * kTotalsPer; base < U;
+         base += (uint64_t)gridDim.x * kLaneB * kTotalsPer)
+        totals_entries<kTotalsPer, kLaneB>(base, U, nbr, owner, row_ptr, tpre, n, T, h);
     h.flush(acc);
 }
 
@@ -770,10 +780,12 @@ __global__ __launch_bounds__(kHubB) __attribute__((amdgpu_waves_per_eu(8, 8))) v
 // --------------------------------------------------------------- batch ----
 // One persistent launch over the work items of many resident graphs.  A
 // workgroup takes items one at a time (per-XCD counters); an item is a slice of
-// one graph's bucket: up to 256 lane-mode dyads (one per thread), up to
-// 4 * kBatchWavePerItem wave-mode dyads (wavefront w takes every fourth), or one
-// group-mode dyad.  Counts go to per-lane bins that are flushed into the
-// graph's 16 accumulators whenever the workgroup moves to another graph.
+// one graph's bucket, over its dyad records or its forward-list edge records:
+// up to 256 lane-mode records (one per thread), up to 4 * kBatchWavePerItem
+// wave-mode records (wavefront w takes every fourth), one group-mode record,
+// one hub task, or a chunk of the totals pass.  Counts go to per-wavefront
+// bins that are flushed into the graph's 16 accumulators whenever the
+// workgroup moves to another graph.
 constexpr int kBatchB = 256;
 constexpr int kBatchWaveTile = 512;
 constexpr int kBatchGroupTile = 2048;
@@ -781,6 +793,46 @@ constexpr int kBatchMergeWords = (4 * 2 * (kBatchWaveTile + 1) > 2 * (kBatchGrou
                                      ? 4 * 2 * (kBatchWaveTile + 1) : 2 * (kBatchGroupTile + 1);
 constexpr int kBatchHubWords = (int)kHubLdsWords;
 constexpr int kBatchTileWords = kBatchMergeWords > kBatchHubWords ? kBatchMergeWords : kBatchHubWords;
+static_assert(kBatchTotalsPerItem % kBatchB == 0, "totals items are whole steps of the workgroup");
+
+template <bool Tri, class H>
+__device__ inline void batch_item(uint32_t kind, const work_item& it, const graph_desc& g, uint32_t* tiles,
+                                  uint32_t* s_xt, const uint8_t* T, H& h) {
+    const uint32_t tid = threadIdx.x, wid = tid >> 6, lane = tid & 63u;
+    const dyad_rec* recs = Tri ? g.edges : g.dyads;
+    const uint32_t* nbr = Tri ? g.fwd : g.nbr;
+    if (kind == kItemLane) {
+        const uint32_t d = it.begin + tid;
+        if (d < it.end) lane_dyad<Tri>(load_rec(recs + d), nbr, g.tpre, g.n, T, h);
+    } else if (kind == kItemWave) {
+        uint32_t* sA = tiles + wid * 2 * (kBatchWaveTile + 1);
+        uint32_t* sB = sA + kBatchWaveTile + 1;
+        for (uint32_t d = it.begin + wid; d < it.end; d += kBatchB / 64) {
+            const dyad_rec r = load_rec(recs + d);
+            dyad_totals t{};
+            if (!Tri && lane == 0) t = load_totals(r, g.tpre);
+            merge_path<64, kBatchWaveTile, wave_sync, Tri>(r, nbr, sA, sB, &s_xt[wid], lane, T, h);
+            if (!Tri && lane == 0) add_totals(r, t, g.n, T, h);
+        }
+    } else if (kind == kItemGroup) {
+        const dyad_rec r = load_rec(recs + it.begin);
+        dyad_totals t{};
+        if (!Tri && tid == 0) t = load_totals(r, g.tpre);
+        merge_path<kBatchB, kBatchGroupTile, block_sync, Tri>(r, nbr, tiles, tiles + kBatchGroupTile + 1, &s_xt[0],
+                                                              tid, T, h);
+        if (!Tri && tid == 0) add_totals(r, t, g.n, T, h);
+    } else {
+        const hub_lds S = hub_carve(tiles);
+        const hub_task* tasks = Tri ? g.edge_tasks : g.hub_tasks;
+        hub_bins_clear(S);
+        uint32_t since = 0;
+        for (uint32_t k = it.begin; k < it.end; ++k) {
+            hub_task_run<Tri>(tasks[k], recs, nbr, g.tpre, g.n, 0u, 0xffffffffu, S, T, h, since);
+            __syncthreads();
+        }
+        hub_bins_flush<Tri>(S, T, h);
+    }
+}
 
 __global__ __launch_bounds__(kBatchB) void k_census_batch(const graph_desc* __restrict__ G,
                                                           const work_item* __restrict__ items,
@@ -796,7 +848,7 @@ __global__ __launch_bounds__(kBatchB) void k_census_batch(const graph_desc* __re
     h.clear();
     const uint32_t count = *num_items;
     const uint32_t xcd = blockIdx.x % kXcds;
-    const uint32_t tid = threadIdx.x, wid = tid >> 6, lane = tid & 63u;
+    const uint32_t tid = threadIdx.x;
     uint32_t cur = 0xffffffffu;
     if (tid == 0) s_next = take_chunk(ctr, xcd);
     __syncthreads();
@@ -815,36 +867,13 @@ __global__ __launch_bounds__(kBatchB) void k_census_batch(const graph_desc* __re
             __syncthreads();
         }
         const graph_desc g = G[it.graph];
-        if (it.kind == kItemLane) {
-            const uint32_t d = it.begin + tid;
-            if (d < it.end) lane_dyad<false>(load_rec(g.dyads + d), g.nbr, g.tpre, g.n, T, h);
-        } else if (it.kind == kItemWave) {
-            uint32_t* sA = tiles + wid * 2 * (kBatchWaveTile + 1);
-            uint32_t* sB = sA + kBatchWaveTile + 1;
-            for (uint32_t d = it.begin + wid; d < it.end; d += kBatchB / 64) {
-                const dyad_rec r = load_rec(g.dyads + d);
-                dyad_totals t{};
-                if (lane == 0) t = load_totals(r, g.tpre);
-                merge_path<64, kBatchWaveTile, wave_sync, false>(r, g.nbr, sA, sB, &s_xt[wid], lane, T, h);
-                if (lane == 0) add_totals(r, t, g.n, T, h);
-            }
-        } else if (it.kind == kItemGroup) {
-            const dyad_rec r = load_rec(g.dyads + it.begin);
-            dyad_totals t{};
-            if (tid == 0) t = load_totals(r, g.tpre);
-            merge_path<kBatchB, kBatchGroupTile, block_sync, false>(r, g.nbr, tiles, tiles + kBatchGroupTile + 1, &s_xt[0],
-                                                              tid, T, h);
-            if (tid == 0) add_totals(r, t, g.n, T, h);
-        } else {
-            const hub_lds S = hub_carve(tiles);
-            hub_bins_clear(S);
-            uint32_t since = 0;
-            for (uint32_t k = it.begin; k < it.end; ++k) {
-                hub_task_run<false>(g.hub_tasks[k], g.dyads, g.nbr, g.tpre, g.n, 0u, 0xffffffffu, S, T, h, since);
-                __syncthreads();
-            }
-            hub_bins_flush<false>(S, T, h);
-        }
+        if (it.kind == kItemTotals)
+            totals_entries<kBatchTotalsPerItem / kBatchB, kBatchB>(it.begin, it.end, g.nbr, g.owner, g.row_ptr,
+                                                                    g.tpre, g.n, T, h);
+        else if (it.kind & kItemTri)
+            batch_item<true>(it.kind & 3u, it, g, tiles, s_xt, T, h);
+        else
+            batch_item<false>(it.kind, it, g, tiles, s_xt, T, h);
         __syncthreads();
         idx = s_next;
         __syncthreads();
@@ -920,7 +949,8 @@ hipError_t census_launch(const device_graph& g, const census_slices& sl, bool tr
     if (tri) {
         if (ev) (void)hipEventRecord(ev[2 * kBuckets], s);
         if (g.U > 0) {
-            uint32_t grid = (uint32_t)std::min<uint64_t>((g.U + 4 * kLaneB - 1) / (4 * kLaneB), cfg.lane_blocks);
+            uint32_t grid = (uint32_t)std::min<uint64_t>((g.U + kTotalsPer * kLaneB - 1) / (kTotalsPer * kLaneB),
+                                                         cfg.lane_blocks);
             size_t sh = sizeof(unsigned long long) * lane_bins<kLaneB>::kWords;
             hipLaunchKernelGGL(k_census_totals, dim3(grid), dim3(kLaneB), sh, s, g.nbr, g.owner, g.row_ptr, g.tpre,
                                g.U, (uint64_t)g.n, table, acc);

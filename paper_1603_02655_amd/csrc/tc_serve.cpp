@@ -196,7 +196,7 @@ bool launch_round(serve_state* S, int si) {
     for (job* j : s.jobs) {
         if (!j->cold) continue;
         bucket_params bp = params_of(ctx->tuning);
-        bp.tri = 0;   // served graphs run through the batched kernel, which uses the dyad records
+        bp.tri = 0;   // cold graphs live for one round: no forward lists (not in their footprint)
         j->status = build_into(j->n, (int64_t)j->src.size(), j->src.data(), j->dst.data(), j->flags, bp, s.stream,
                                &j->built, nullptr);
         std::vector<int32_t>().swap(j->src);
@@ -207,12 +207,12 @@ bool launch_round(serve_state* S, int si) {
     for (size_t i = 0; i < s.jobs.size(); ++i) {
         job* j = s.jobs[i];
         if (j->status != TC_OK) {
-            descs[i] = graph_desc{nullptr, nullptr, nullptr, 0, nullptr, 0};
+            descs[i] = graph_desc{};
             continue;
         }
         const device_graph& g = j->cold ? j->built : j->g->g;
-        descs[i] = graph_desc{g.dyads, g.nbr, g.tpre, (uint64_t)g.n, g.hub_tasks, 0};
-        append_items(g, (uint32_t)i, items);
+        descs[i] = describe(g);
+        append_items(g, (uint32_t)i, ctx->tuning.tri && g.tri.fwd_ptr, items);
     }
     hipError_t e = slot_reserve(s, (uint32_t)s.jobs.size(), (uint32_t)items.size());
     if (e == hipSuccess) {

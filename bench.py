@@ -13,6 +13,7 @@ the 003 finalisation).  Prints one JSON line.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -29,6 +30,37 @@ HBM_PEAK_GBS = 8000.0
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def census_source_hash() -> str:
+    """sha256 (first 16 hex digits) of the library sources, in name order: a
+    counter summary taken on other sources no longer describes the kernels."""
+    d = os.path.join(ROOT, "paper_1603_02655_amd", "csrc")
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(d)):
+        if name.endswith((".hip", ".h", ".cpp")):
+            with open(os.path.join(d, name), "rb") as f:
+                h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload_key: str, kernel: str):
+    """HBM bytes per launch of `kernel` (FETCH_SIZE and WRITE_SIZE, scaled by
+    the copy calibration) from profiles/hbm_traffic_<workload>.md, when that
+    table was taken on the current sources; None otherwise."""
+    path = os.path.join(ROOT, "profiles", f"hbm_traffic_{workload_key}.md")
+    if not os.path.exists(path):
+        return None
+    src = census_source_hash()
+    with open(path) as f:
+        for line in f:
+            cells = [c.strip().strip("`") for c in line.strip().strip("|").split("|")]
+            if len(cells) >= 7 and cells[0] == kernel and cells[1] == src:
+                try:
+                    return float(cells[6])
+                except ValueError:
+                    return None
+    return None
 
 
 def workload(name: str):
@@ -427,8 +459,11 @@ def main():
                    "sum_d2": info["sum_d2"], "max_degree": info["max_degree"],
                    "tuning": ctx.get_tuning()},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": dom_name, "bytes_per_launch": bytes_dom, "kernel_ms": dom_ms},
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(args.workload, dom_name + ("<true>" if tri else "<false>")
+                                                 if dom_name != "k_census_totals" else dom_name),
+                     "kernel": dom_name, "bytes_per_launch": bytes_dom, "kernel_ms": dom_ms,
+                     "source_hash": census_source_hash()},
         "path": "forward-list triangles" if tri else "dyad intersections",
         "kernels_ms": per_launch_ms,
         "kernel_bytes": bytes_of,

@@ -518,16 +518,20 @@ __device__ inline void hub_insert(uint32_t* hash, uint32_t e) {
     }
 }
 
+// The whole bucket is read at once and its four slots compared without
+// branches (a vertex is stored at most once); the next bucket is read only
+// when this one is full and holds no match.
 __device__ inline uint32_t hub_probe(const uint32_t* hash, uint32_t w) {
     const uint4* h4 = reinterpret_cast<const uint4*>(hash);
     uint32_t b = hub_bucket(w);
     for (;;) {
         const uint4 q = h4[b];
-        if ((q.x >> 2) == w) return q.x;
-        if ((q.y >> 2) == w) return q.y;
-        if ((q.z >> 2) == w) return q.z;
-        if ((q.w >> 2) == w) return q.w;
-        if (q.w == kEmpty) return kEmpty;
+        uint32_t r = kEmpty;
+        r = (q.x >> 2) == w ? q.x : r;
+        r = (q.y >> 2) == w ? q.y : r;
+        r = (q.z >> 2) == w ? q.z : r;
+        r = (q.w >> 2) == w ? q.w : r;
+        if (r != kEmpty || q.w == kEmpty) return r;
         b = (b + 1) & (kHubBuckets - 1);
     }
 }
@@ -709,10 +713,17 @@ __device__ inline void hub_task_run(const hub_task& tk, const dyad_rec* __restri
                     mk[k] = m;
                     if (ff < q1) {
                         if (ff >= next) {
-                            do {
+                            // the next four record starts are read together;
+                            // off[nrec] = P > ff bounds the look-ahead
+                            const uint32_t o2 = S.off[min(i + 2, nrec)], o3 = S.off[min(i + 3, nrec)];
+                            const uint32_t o4 = S.off[min(i + 4, nrec)], o5 = S.off[min(i + 5, nrec)];
+                            i += 1u + (ff >= o2 ? 1u : 0u) + (ff >= o3 ? 1u : 0u) + (ff >= o4 ? 1u : 0u) +
+                                 (ff >= o5 ? 1u : 0u);
+                            next = S.off[i + 1];
+                            while (ff >= next) {
                                 ++i;
                                 next = S.off[i + 1];
-                            } while (ff >= next);
+                            }
                             base = S.pos[i] - S.off[i];
                             m = S.meta[i];
                         }

@@ -225,18 +225,32 @@ __device__ inline void lane_dyad(const dyad_rec& r, const uint32_t* __restrict__
     if constexpr (!Tri) add_totals(r, t, n, T, h);
 }
 
+// Dyad records add their per-dyad terms on every record: per-lane bins (in
+// dynamic LDS).  Forward-list edge records only add on a triangle, which is
+// rare per record: per-wavefront bins, and far less LDS.
 template <bool Tri>
 __global__ __launch_bounds__(kLaneB) void k_census_lane(census_args L) {
     extern __shared__ unsigned long long lds[];
     __shared__ uint8_t T[64];
+    __shared__ unsigned long long wbins[Tri ? wave_bins<kLaneB>::kWords : 1];
     if (threadIdx.x < 64) T[threadIdx.x] = L.table[threadIdx.x];
-    lane_bins<kLaneB> h{lds};
-    h.clear();
-    __syncthreads();
-    for (uint64_t d = (uint64_t)blockIdx.x * kLaneB + threadIdx.x; d < L.count;
-         d += (uint64_t)gridDim.x * kLaneB)
-        lane_dyad<Tri>(load_rec(L.dyads + d), L.nbr, L.tpre, L.n, T, h);
-    h.flush(L.acc);
+    if constexpr (Tri) {
+        wave_bins<kLaneB> h{wbins};
+        h.clear();
+        __syncthreads();
+        for (uint64_t d = (uint64_t)blockIdx.x * kLaneB + threadIdx.x; d < L.count;
+             d += (uint64_t)gridDim.x * kLaneB)
+            lane_dyad<Tri>(load_rec(L.dyads + d), L.nbr, L.tpre, L.n, T, h);
+        h.flush(L.acc);
+    } else {
+        lane_bins<kLaneB> h{lds};
+        h.clear();
+        __syncthreads();
+        for (uint64_t d = (uint64_t)blockIdx.x * kLaneB + threadIdx.x; d < L.count;
+             d += (uint64_t)gridDim.x * kLaneB)
+            lane_dyad<Tri>(load_rec(L.dyads + d), L.nbr, L.tpre, L.n, T, h);
+        h.flush(L.acc);
+    }
 }
 
 // The per-dyad terms that need no intersection, for every dyad at once (the
@@ -288,6 +302,18 @@ __device__ inline void totals_entries(uint64_t base, uint64_t end, const uint32_
 }
 
 constexpr uint32_t kTotalsPer = 4;   // entries per thread and step
+constexpr uint32_t kTotalsSlots = 8; // distinct bins the totals pass can reach (any table here has <= 8)
+
+// Per-lane bins over a few slots: the totals pass reaches only the bins of the
+// codes f, f | t << 2 and f | t << 4 (f, t in 1..3), at most kTotalsSlots of
+// them, so a lane keeps one 64-bit slot per reachable bin (16 KB of LDS for
+// 256 lanes instead of 35 KB).  The codes are remapped to slots in a table.
+struct slot_bins {
+    unsigned long long* bins;   // kTotalsSlots x kLaneB
+    __device__ inline void add(uint32_t slot, unsigned long long x) {
+        atomicAdd(&bins[slot * kLaneB + threadIdx.x], x);
+    }
+};
 
 __global__ __launch_bounds__(kLaneB) void k_census_totals(const uint32_t* __restrict__ nbr,
                                                           const uint32_t* __restrict__ owner,
@@ -295,16 +321,57 @@ __global__ __launch_bounds__(kLaneB) void k_census_totals(const uint32_t* __rest
                                                           const uint64_t* __restrict__ tpre, uint64_t U, uint64_t n,
                                                           const uint8_t* __restrict__ table,
                                                           unsigned long long* __restrict__ acc) {
-    extern __shared__ unsigned long long lds[];
-    __shared__ uint8_t T[64];
+    __shared__ unsigned long long sbins[kTotalsSlots * kLaneB];
+    __shared__ unsigned long long wbins[wave_bins<kLaneB>::kWords];
+    __shared__ uint8_t T[64], TS[64];
+    __shared__ uint32_t bin_of_slot[kTotalsSlots], s_nslots;
     if (threadIdx.x < 64) T[threadIdx.x] = table[threadIdx.x];
-    lane_bins<kLaneB> h{lds};
-    h.clear();
     __syncthreads();
-    for (uint64_t base = (uint64_t)blockIdx.x * kLaneB * kTotalsPer; base < U;
-         base += (uint64_t)gridDim.x * kLaneB * kTotalsPer)
-        totals_entries<kTotalsPer, kLaneB>(base, U, nbr, owner, row_ptr, tpre, n, T, h);
-    h.flush(acc);
+    if (threadIdx.x == 0) {
+        // slots of the reachable bins, in order of first use
+        uint32_t ns = 0;
+        for (uint32_t c = 0; c < 64; ++c) TS[c] = 0xff;
+        for (uint32_t f = 1; f < 4; ++f)
+            for (uint32_t j = 0; j < 7; ++j) {
+                const uint32_t c = j == 0 ? f : (j <= 3 ? f | (j << 2) : f | ((j - 3) << 4));
+                uint32_t sl = 0;
+                while (sl < ns && bin_of_slot[sl] != T[c]) ++sl;
+                if (sl == ns && ns < kTotalsSlots) bin_of_slot[ns++] = T[c];
+                TS[c] = sl < ns ? (uint8_t)sl : (uint8_t)0xff;
+            }
+        bool all = true;
+        for (uint32_t f = 1; f < 4; ++f)
+            for (uint32_t j = 0; j < 7; ++j) {
+                const uint32_t c = j == 0 ? f : (j <= 3 ? f | (j << 2) : f | ((j - 3) << 4));
+                all = all && TS[c] != 0xff;
+            }
+        s_nslots = all ? ns : 0;   // 0: more bins than slots, use per-wavefront bins
+    }
+    for (uint32_t k = threadIdx.x; k < kTotalsSlots * kLaneB; k += kLaneB) sbins[k] = 0;
+    wave_bins<kLaneB> hw{wbins};
+    hw.clear();
+    __syncthreads();
+    const uint32_t nslots = s_nslots;
+    if (nslots) {
+        slot_bins hs{sbins};
+        for (uint64_t base = (uint64_t)blockIdx.x * kLaneB * kTotalsPer; base < U;
+             base += (uint64_t)gridDim.x * kLaneB * kTotalsPer)
+            totals_entries<kTotalsPer, kLaneB>(base, U, nbr, owner, row_ptr, tpre, n, TS, hs);
+        __syncthreads();
+        // slot sums: wavefront w sums slots w, w + 4 over the workgroup's lanes
+        const uint32_t lane = threadIdx.x & 63u;
+        for (uint32_t sl = threadIdx.x >> 6; sl < nslots; sl += kLaneB / 64) {
+            unsigned long long v = 0;
+            for (uint32_t i = lane; i < kLaneB; i += 64) v += sbins[sl * kLaneB + i];
+            for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+            if (lane == 0 && v != 0 && bin_of_slot[sl] < kNumClasses) atomicAdd(&acc[bin_of_slot[sl]], v);
+        }
+    } else {
+        for (uint64_t base = (uint64_t)blockIdx.x * kLaneB * kTotalsPer; base < U;
+             base += (uint64_t)gridDim.x * kLaneB * kTotalsPer)
+            totals_entries<kTotalsPer, kLaneB>(base, U, nbr, owner, row_ptr, tpre, n, T, hw);
+        hw.flush(acc);
+    }
 }
 
 // ---------------------------------------------------------- merge path ----
@@ -928,7 +995,7 @@ void launch_bucket(int b, const census_args& L, uint64_t cnt, const census_confi
                    hipStream_t s) {
     if (b == 0) {
         uint32_t grid = (uint32_t)std::min<uint64_t>((cnt + kLaneB - 1) / kLaneB, cfg.lane_blocks);
-        size_t sh = sizeof(unsigned long long) * lane_bins<kLaneB>::kWords;
+        size_t sh = Tri ? 0 : sizeof(unsigned long long) * lane_bins<kLaneB>::kWords;
         hipLaunchKernelGGL(k_census_lane<Tri>, dim3(grid), dim3(kLaneB), sh, s, L);
     } else if (b == 1) {
         uint32_t grid = (uint32_t)std::min<uint64_t>(cnt, cfg.wave_blocks);
@@ -962,8 +1029,7 @@ hipError_t census_launch(const device_graph& g, const census_slices& sl, bool tr
         if (g.U > 0) {
             uint32_t grid = (uint32_t)std::min<uint64_t>((g.U + kTotalsPer * kLaneB - 1) / (kTotalsPer * kLaneB),
                                                          cfg.lane_blocks);
-            size_t sh = sizeof(unsigned long long) * lane_bins<kLaneB>::kWords;
-            hipLaunchKernelGGL(k_census_totals, dim3(grid), dim3(kLaneB), sh, s, g.nbr, g.owner, g.row_ptr, g.tpre,
+            hipLaunchKernelGGL(k_census_totals, dim3(grid), dim3(kLaneB), 0, s, g.nbr, g.owner, g.row_ptr, g.tpre,
                                g.U, (uint64_t)g.n, table, acc);
         }
         if (ev) (void)hipEventRecord(ev[2 * kBuckets + 1], s);

@@ -755,44 +755,72 @@ __device__ inline void hub_task_run(const hub_task& tk, const dyad_rec* __restri
         block_scan_u32(S.off, nrec, S.wsum);
         const uint32_t P = S.off[nrec];
         // Wavefront w takes the w-th quarter [q0, q1) of the flattened list and
-        // walks it in windows of 64 consecutive entries, so every gather reads
-        // 64 adjacent words; a lane keeps the record of its current entry and
-        // moves it forward as the windows pass record boundaries.
+        // walks it in windows of 64 * kHubGather entries; lane l takes the
+        // kHubGather consecutive entries at l * kHubGather of each window, so a
+        // wavefront's gathers stay within 64 * kHubGather adjacent words.  A
+        // lane keeps the record of its current entry and, prefetched, the
+        // start, position and meta word of the record after it: moving to the
+        // next record waits on no LDS read.
         const uint32_t lane = tid & 63u, wid = tid >> 6;
         constexpr uint32_t kWaves = kHubB / 64;
         const uint32_t q0 = (uint32_t)(((uint64_t)P * wid) / kWaves), q1 = (uint32_t)(((uint64_t)P * (wid + 1)) / kWaves);
-        const uint32_t per = (P + kHubB - 1) / kHubB + 1;   // bound on a lane's probes in this tile
-        const uint32_t first = q0 + lane;
-        if (first < q1) {
-            uint32_t lo = 0, hi = nrec;                 // record holding `first`: off[i] <= first < off[i+1]
-            while (hi - lo > 1) {
-                const uint32_t mid = (lo + hi) >> 1;
-                if (S.off[mid] <= first) lo = mid; else hi = mid;
+        const uint32_t per = (P + kHubB - 1) / kHubB + kHubGather;   // bound on a lane's probes in this tile
+        if (q0 + kHubGather * lane < q1) {
+            uint32_t i = 0;
+            {
+                const uint32_t first = q0 + kHubGather * lane;
+                uint32_t hi = nrec;                     // record holding `first`: off[i] <= first < off[i+1]
+                while (hi - i > 1) {
+                    const uint32_t mid = (i + hi) >> 1;
+                    if (S.off[mid] <= first) i = mid; else hi = mid;
+                }
             }
-            uint32_t i = lo;
             uint32_t next = S.off[i + 1], base = S.pos[i] - S.off[i], m = S.meta[i];
-            for (uint32_t f = first; f < q1; f += 64u * kHubGather) {
+            uint32_t n_next = S.off[min(i + 2, nrec)], n_pos = S.pos[min(i + 1, nrec - 1)];
+            uint32_t n_m = S.meta[min(i + 1, nrec - 1)];
+            // record of ff >= off[i], any number of records ahead
+            auto seek = [&](uint32_t ff) {
+                // the next four record starts are read together; off[nrec] = P > ff bounds the look-ahead
+                const uint32_t o2 = S.off[min(i + 2, nrec)], o3 = S.off[min(i + 3, nrec)];
+                const uint32_t o4 = S.off[min(i + 4, nrec)], o5 = S.off[min(i + 5, nrec)];
+                i += 1u + (ff >= o2 ? 1u : 0u) + (ff >= o3 ? 1u : 0u) + (ff >= o4 ? 1u : 0u) + (ff >= o5 ? 1u : 0u);
+                next = S.off[i + 1];
+                while (ff >= next) {
+                    ++i;
+                    next = S.off[i + 1];
+                }
+                base = S.pos[i] - S.off[i];
+                m = S.meta[i];
+                n_next = S.off[min(i + 2, nrec)];
+                n_pos = S.pos[min(i + 1, nrec - 1)];
+                n_m = S.meta[min(i + 1, nrec - 1)];
+            };
+            for (uint32_t win = q0; win < q1; win += 64u * kHubGather) {
+                const uint32_t g0 = win + kHubGather * lane;
+                if (g0 < q1 && g0 >= next) seek(g0);
                 uint32_t e[kHubGather], mk[kHubGather];
 #pragma unroll
                 for (uint32_t k = 0; k < kHubGather; ++k) {
-                    const uint32_t ff = f + 64u * k;
+                    const uint32_t ff = g0 + k;
                     e[k] = kEmpty;
                     mk[k] = m;
                     if (ff < q1) {
                         if (ff >= next) {
-                            // the next four record starts are read together;
-                            // off[nrec] = P > ff bounds the look-ahead
-                            const uint32_t o2 = S.off[min(i + 2, nrec)], o3 = S.off[min(i + 3, nrec)];
-                            const uint32_t o4 = S.off[min(i + 4, nrec)], o5 = S.off[min(i + 5, nrec)];
-                            i += 1u + (ff >= o2 ? 1u : 0u) + (ff >= o3 ? 1u : 0u) + (ff >= o4 ? 1u : 0u) +
-                                 (ff >= o5 ? 1u : 0u);
-                            next = S.off[i + 1];
-                            while (ff >= next) {
-                                ++i;
-                                next = S.off[i + 1];
+                            // the record after i, from the prefetched words
+                            const uint32_t start = next;
+                            ++i;
+                            base = n_pos - start;
+                            m = n_m;
+                            next = n_next;
+                            if (ff >= next) {
+                                --i;                    // records without entries here: walk on from i
+                                next = start;
+                                seek(ff);
+                            } else {
+                                n_next = S.off[min(i + 2, nrec)];
+                                n_pos = S.pos[min(i + 1, nrec - 1)];
+                                n_m = S.meta[min(i + 1, nrec - 1)];
                             }
-                            base = S.pos[i] - S.off[i];
-                            m = S.meta[i];
                         }
                         mk[k] = m;
                         e[k] = nbr[base + ff];

@@ -39,8 +39,25 @@ def _compile(src: str) -> str:
     return obj
 
 
+CPU_SRC = os.path.join(PKG, "cpu", "tc_cpu.cpp")
+CPU_LIB_PATH = os.path.join(PKG, "libtc_cpu.so")
+
+
+def build_cpu() -> str:
+    """Compiles the multicore CPU census (libtc_cpu.so) with the host compiler."""
+    tmp = CPU_LIB_PATH + ".tmp"
+    cmd = ["g++", "-O3", "-std=c++17", "-fPIC", "-shared", "-pthread", "-Wall",
+           "-I", os.path.join(ROOT, "include"), CPU_SRC, "-o", tmp]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"g++ failed on tc_cpu.cpp:\n{r.stdout}\n{r.stderr}")
+    os.replace(tmp, CPU_LIB_PATH)
+    return CPU_LIB_PATH
+
+
 def build(jobs: int = 8) -> str:
-    """Compiles every source and links libtc.so; always rebuilds."""
+    """Compiles every source and links libtc.so (and libtc_cpu.so); always rebuilds."""
+    build_cpu()
     os.makedirs(BUILD_DIR, exist_ok=True)
     srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
     with ThreadPoolExecutor(max_workers=max(1, min(jobs, len(srcs)))) as ex:

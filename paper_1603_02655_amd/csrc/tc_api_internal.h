@@ -76,7 +76,7 @@ inline tc_tuning default_tuning(int cu_count) {
     t.lane_blocks = (uint32_t)cu * 8;
     t.wave_blocks = (uint32_t)cu * 10;
     t.group_blocks = (uint32_t)cu * 2;
-    t.batch_blocks = (uint32_t)cu * 3;
+    t.batch_blocks = (uint32_t)cu * 4;
     t.hub_blocks = (uint32_t)cu * 8;
     t.tri = 1;      // whole-graph census through the triangles of the forward lists
     return t;

@@ -122,13 +122,17 @@ def bench_batch(args):
     hs = [ctx.build_graph(g.n, g.src, g.dst) for g in pool]
     arcs = sum(int(h.info["arcs_kept"]) for h in hs)
     rng = np.random.default_rng(1)
-    sample = [hs[i] for i in rng.choice(len(hs), size=min(64, len(hs)), replace=False)]
-    t = time.perf_counter()
-    tuning = ctx.autotune(sample)
-    tune_s = time.perf_counter() - t
-    for h in hs:
-        ctx.rebucket(h)
-    log(f"[bench] autotuned in {tune_s:.1f}s: {tuning}")
+    tune_s = 0.0
+    if args.autotune_sample > 0:
+        sample = [hs[i] for i in rng.choice(len(hs), size=min(args.autotune_sample, len(hs)), replace=False)]
+        t = time.perf_counter()
+        tuning = ctx.autotune(sample)
+        tune_s = time.perf_counter() - t
+        for h in hs:
+            ctx.rebucket(h)
+        log(f"[bench] autotuned in {tune_s:.1f}s: {tuning}")
+    else:
+        tuning = ctx.get_tuning()
     each = ctx.census_each(hs)
     tc.device_synchronize(0)
     t = time.perf_counter()
@@ -379,6 +383,8 @@ def main():
     ap.add_argument("--rate", default="2000", help="comma-separated arrival rates (requests/s)")
     ap.add_argument("--duration", type=float, default=5.0)
     ap.add_argument("--pool", type=int, default=64)
+    ap.add_argument("--autotune-sample", type=int, default=256,
+                    help="graphs the batched bench autotunes on (0: keep the default tuning)")
     ap.add_argument("--tuning", default="", help="comma-separated key=value overrides, e.g. t_hub=256")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="also run 3 device-to-device copies of this many bytes (counter calibration)")

@@ -42,7 +42,7 @@ struct work_item {
     uint32_t graph, kind, begin, end;   // records [begin, end) of graph `graph`'s record array;
                                         // hub items: hub tasks [begin, end) of the graph
 };
-constexpr uint32_t kBatchTotalsPerItem = 1024;   // neighbour entries per totals item
+constexpr uint32_t kBatchTotalsPerItem = 4096;   // neighbour entries per totals item
 constexpr uint32_t kBatchLanePerItem = 256;   // one dyad per thread of a 256-thread workgroup
 constexpr uint32_t kBatchWavePerItem = 16;    // four wavefronts, four dyads each
 

@@ -308,12 +308,53 @@ constexpr uint32_t kTotalsSlots = 8; // distinct bins the totals pass can reach 
 // codes f, f | t << 2 and f | t << 4 (f, t in 1..3), at most kTotalsSlots of
 // them, so a lane keeps one 64-bit slot per reachable bin (16 KB of LDS for
 // 256 lanes instead of 35 KB).  The codes are remapped to slots in a table.
+// Adds straight to a graph's 16 accumulators in global memory.
+struct global_bins {
+    unsigned long long* acc;
+    __device__ inline void add(uint32_t cls, unsigned long long x) { atomicAdd(&acc[cls], x); }
+};
+
 struct slot_bins {
     unsigned long long* bins;   // kTotalsSlots x kLaneB
     __device__ inline void add(uint32_t slot, unsigned long long x) {
         atomicAdd(&bins[slot * kLaneB + threadIdx.x], x);
     }
 };
+
+// Fills TS (code -> slot) and bin_of_slot for the reachable codes of table T;
+// returns the number of slots, or 0 when more than kTotalsSlots bins are
+// reachable.  One thread.
+__device__ inline uint32_t totals_slots(const uint8_t* T, uint8_t* TS, uint32_t* bin_of_slot) {
+    uint32_t ns = 0;
+    bool all = true;
+    for (uint32_t c = 0; c < 64; ++c) TS[c] = 0xff;
+    for (uint32_t f = 1; f < 4; ++f)
+        for (uint32_t j = 0; j < 7; ++j) {
+            const uint32_t c = j == 0 ? f : (j <= 3 ? f | (j << 2) : f | ((j - 3) << 4));
+            uint32_t sl = 0;
+            while (sl < ns && bin_of_slot[sl] != T[c]) ++sl;
+            if (sl == ns && ns < kTotalsSlots) bin_of_slot[ns++] = T[c];
+            TS[c] = sl < ns ? (uint8_t)sl : (uint8_t)0xff;
+            all = all && sl < ns;
+        }
+    return all ? ns : 0u;
+}
+
+// Sums the per-lane slots over a kLaneB workgroup into h (wavefront w takes
+// slots w, w + 4) and clears them.
+template <class H>
+__device__ inline void slots_flush(unsigned long long* sbins, const uint32_t* bin_of_slot, uint32_t nslots, H& h) {
+    __syncthreads();
+    const uint32_t lane = threadIdx.x & 63u;
+    for (uint32_t sl = threadIdx.x >> 6; sl < nslots; sl += kLaneB / 64) {
+        unsigned long long v = 0;
+        for (uint32_t i = lane; i < kLaneB; i += 64) v += sbins[sl * kLaneB + i];
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        if (lane == 0 && v != 0 && bin_of_slot[sl] < kNumClasses) h.add(bin_of_slot[sl], v);
+    }
+    __syncthreads();
+    for (uint32_t k = threadIdx.x; k < kTotalsSlots * kLaneB; k += kLaneB) sbins[k] = 0;
+}
 
 __global__ __launch_bounds__(kLaneB) void k_census_totals(const uint32_t* __restrict__ nbr,
                                                           const uint32_t* __restrict__ owner,
@@ -327,26 +368,7 @@ __global__ __launch_bounds__(kLaneB) void k_census_totals(const uint32_t* __rest
     __shared__ uint32_t bin_of_slot[kTotalsSlots], s_nslots;
     if (threadIdx.x < 64) T[threadIdx.x] = table[threadIdx.x];
     __syncthreads();
-    if (threadIdx.x == 0) {
-        // slots of the reachable bins, in order of first use
-        uint32_t ns = 0;
-        for (uint32_t c = 0; c < 64; ++c) TS[c] = 0xff;
-        for (uint32_t f = 1; f < 4; ++f)
-            for (uint32_t j = 0; j < 7; ++j) {
-                const uint32_t c = j == 0 ? f : (j <= 3 ? f | (j << 2) : f | ((j - 3) << 4));
-                uint32_t sl = 0;
-                while (sl < ns && bin_of_slot[sl] != T[c]) ++sl;
-                if (sl == ns && ns < kTotalsSlots) bin_of_slot[ns++] = T[c];
-                TS[c] = sl < ns ? (uint8_t)sl : (uint8_t)0xff;
-            }
-        bool all = true;
-        for (uint32_t f = 1; f < 4; ++f)
-            for (uint32_t j = 0; j < 7; ++j) {
-                const uint32_t c = j == 0 ? f : (j <= 3 ? f | (j << 2) : f | ((j - 3) << 4));
-                all = all && TS[c] != 0xff;
-            }
-        s_nslots = all ? ns : 0;   // 0: more bins than slots, use per-wavefront bins
-    }
+    if (threadIdx.x == 0) s_nslots = totals_slots(T, TS, bin_of_slot);
     for (uint32_t k = threadIdx.x; k < kTotalsSlots * kLaneB; k += kLaneB) sbins[k] = 0;
     wave_bins<kLaneB> hw{wbins};
     hw.clear();
@@ -357,15 +379,8 @@ __global__ __launch_bounds__(kLaneB) void k_census_totals(const uint32_t* __rest
         for (uint64_t base = (uint64_t)blockIdx.x * kLaneB * kTotalsPer; base < U;
              base += (uint64_t)gridDim.x * kLaneB * kTotalsPer)
             totals_entries<kTotalsPer, kLaneB>(base, U, nbr, owner, row_ptr, tpre, n, TS, hs);
-        __syncthreads();
-        // slot sums: wavefront w sums slots w, w + 4 over the workgroup's lanes
-        const uint32_t lane = threadIdx.x & 63u;
-        for (uint32_t sl = threadIdx.x >> 6; sl < nslots; sl += kLaneB / 64) {
-            unsigned long long v = 0;
-            for (uint32_t i = lane; i < kLaneB; i += 64) v += sbins[sl * kLaneB + i];
-            for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-            if (lane == 0 && v != 0 && bin_of_slot[sl] < kNumClasses) atomicAdd(&acc[bin_of_slot[sl]], v);
-        }
+        global_bins g{acc};
+        slots_flush(sbins, bin_of_slot, nslots, g);
     } else {
         for (uint64_t base = (uint64_t)blockIdx.x * kLaneB * kTotalsPer; base < U;
              base += (uint64_t)gridDim.x * kLaneB * kTotalsPer)
@@ -900,6 +915,8 @@ constexpr int kBatchMergeWords = (4 * 2 * (kBatchWaveTile + 1) > 2 * (kBatchGrou
 constexpr int kBatchHubWords = (int)kHubLdsWords;
 constexpr int kBatchTileWords = kBatchMergeWords > kBatchHubWords ? kBatchMergeWords : kBatchHubWords;
 static_assert(kBatchTotalsPerItem % kBatchB == 0, "totals items are whole steps of the workgroup");
+static_assert(kBatchB == kLaneB, "the slot helpers assume 256-lane workgroups");
+static_assert(2 * kTotalsSlots * kBatchB <= kBatchTileWords, "per-lane slots fit in the tile area");
 
 template <bool Tri, class H>
 __device__ inline void batch_item(uint32_t kind, const work_item& it, const graph_desc& g, uint32_t* tiles,
@@ -947,9 +964,11 @@ __global__ __launch_bounds__(kBatchB) void k_census_batch(const graph_desc* __re
                                                           unsigned int* __restrict__ ctr) {
     __shared__ __attribute__((aligned(16))) uint32_t tiles[kBatchTileWords];
     __shared__ unsigned long long bins[wave_bins<kBatchB>::kWords];
-    __shared__ uint8_t T[64];
-    __shared__ uint32_t s_xt[kBatchB / 64], s_next;
+    __shared__ uint8_t T[64], TS[64];
+    __shared__ uint32_t s_xt[kBatchB / 64], s_next, bin_of_slot[kTotalsSlots], s_nslots;
     if (threadIdx.x < 64) T[threadIdx.x] = c_table[threadIdx.x];
+    __syncthreads();
+    if (threadIdx.x == 0) s_nslots = totals_slots(T, TS, bin_of_slot);
     wave_bins<kBatchB> h{bins};
     h.clear();
     const uint32_t count = *num_items;
@@ -973,9 +992,24 @@ __global__ __launch_bounds__(kBatchB) void k_census_batch(const graph_desc* __re
             __syncthreads();
         }
         const graph_desc g = G[it.graph];
-        if (it.kind == kItemTotals)
-            totals_entries<kBatchTotalsPerItem / kBatchB, kBatchB>(it.begin, it.end, g.nbr, g.owner, g.row_ptr,
-                                                                    g.tpre, g.n, T, h);
+        if (it.kind == kItemTotals) {
+            // per-lane slots in the (idle) tile area, summed into the
+            // wavefront bins at the end of the item
+            const uint32_t nslots = s_nslots;
+            if (nslots) {
+                unsigned long long* sbins = reinterpret_cast<unsigned long long*>(tiles);
+                for (uint32_t k = tid; k < kTotalsSlots * kBatchB; k += kBatchB) sbins[k] = 0;
+                __syncthreads();
+                slot_bins hs{sbins};
+                for (uint32_t b0 = it.begin; b0 < it.end; b0 += kTotalsPer * kBatchB)
+                    totals_entries<kTotalsPer, kBatchB>(b0, it.end, g.nbr, g.owner, g.row_ptr, g.tpre, g.n, TS,
+                                                        hs);
+                slots_flush(sbins, bin_of_slot, nslots, h);
+            } else {
+                for (uint32_t b0 = it.begin; b0 < it.end; b0 += kTotalsPer * kBatchB)
+                    totals_entries<kTotalsPer, kBatchB>(b0, it.end, g.nbr, g.owner, g.row_ptr, g.tpre, g.n, T, h);
+            }
+        }
         else if (it.kind & kItemTri)
             batch_item<true>(it.kind & 3u, it, g, tiles, s_xt, T, h);
         else

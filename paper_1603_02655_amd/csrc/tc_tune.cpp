@@ -149,7 +149,7 @@ extern "C" int tc_autotune(tc_context ctx, const tc_graph* sample, int32_t count
     const std::vector<uint32_t> hubt = {32, 64, 128, 256, 512, 1024, 4096, kInf};
     const std::vector<uint32_t> hubb = {cu * 2, cu * 3, cu * 5, cu * 8};
     const std::vector<uint32_t> tris = {0, 1};
-    const int reps = 2;
+    const int reps = 3;
 
     rc = apply(ctx, sample, count, best);
     double best_s = 0;

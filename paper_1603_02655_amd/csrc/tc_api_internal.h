@@ -84,7 +84,8 @@ inline tc_tuning default_tuning(int cu_count) {
 
 // batched mode (tc_batch.hip)
 graph_desc describe(const device_graph& g);
-void append_items(const device_graph& g, uint32_t gi, bool tri, std::vector<work_item>& out);
+void append_items(const device_graph& g, uint32_t gi, bool tri, std::vector<work_item>& hub,
+                  std::vector<work_item>& out);
 void batch_release_all(tc_context_s* ctx);
 void batch_forget_graph_locked(tc_context_s* ctx, tc_graph g);
 

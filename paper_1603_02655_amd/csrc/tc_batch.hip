@@ -23,7 +23,7 @@ struct batch_plan {
     unsigned long long* h_accs = nullptr;   // pinned
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    uint32_t grid = 0;
+    uint32_t grid = 0, hub_grid = 0;
     bool valid = false;                     // buffers describe `graphs`
     bool tri = false;                       // ... through their forward lists
 
@@ -73,10 +73,11 @@ graph_desc describe(const device_graph& g) {
     return d;
 }
 
-// Work items of one graph: hub tasks and group-mode records first (largest),
-// then wave-mode chunks, then lane-mode chunks; over the forward-list edge
-// records (after the totals chunks) when `tri`.
-void append_items(const device_graph& g, uint32_t gi, bool tri, std::vector<work_item>& out) {
+// Work items of one graph: hub tasks into `hub`; into `out` the totals chunks
+// (when `tri`), then group-mode records (largest), wave-mode chunks and
+// lane-mode chunks, over the forward-list edge records when `tri`.
+void append_items(const device_graph& g, uint32_t gi, bool tri, std::vector<work_item>& hub,
+                  std::vector<work_item>& out) {
     const uint64_t* off = g.bucket_off;
     uint32_t ntasks = g.n_hub_tasks, flag = 0;
     if (tri) {
@@ -87,7 +88,7 @@ void append_items(const device_graph& g, uint32_t gi, bool tri, std::vector<work
         ntasks = g.tri.edges.n_tasks;
         flag = kItemTri;
     }
-    for (uint32_t t = 0; t < ntasks; ++t) out.push_back(work_item{gi, kItemHub | flag, t, t + 1});
+    for (uint32_t t = 0; t < ntasks; ++t) hub.push_back(work_item{gi, kItemHub | flag, t, t + 1});
     for (uint64_t d = off[2]; d < off[3]; ++d)
         out.push_back(work_item{gi, kItemGroup | flag, (uint32_t)d, (uint32_t)d + 1});
     for (uint64_t d = off[1]; d < off[2]; d += kBatchWavePerItem)
@@ -100,16 +101,19 @@ void append_items(const device_graph& g, uint32_t gi, bool tri, std::vector<work
 
 namespace {
 
-hipError_t ensure_capacity(batch_plan* p, uint32_t graphs, uint32_t items, hipStream_t s, uint32_t grid) {
-    if (p->exec && graphs <= p->cap_graphs && items <= p->cap_items && grid == p->grid) return hipSuccess;
+hipError_t ensure_capacity(batch_plan* p, uint32_t graphs, uint32_t items, hipStream_t s, uint32_t grid,
+                           uint32_t hub_grid) {
+    if (p->exec && graphs <= p->cap_graphs && items <= p->cap_items && grid == p->grid && hub_grid == p->hub_grid)
+        return hipSuccess;
     (void)hipStreamSynchronize(s);
     p->release();
     p->cap_graphs = std::max<uint32_t>(graphs + graphs / 4, 16);
     p->cap_items = std::max<uint32_t>(items + items / 4, 1024);
     p->grid = grid;
+    p->hub_grid = hub_grid;
     hipError_t e = hipMalloc((void**)&p->d_desc, sizeof(graph_desc) * p->cap_graphs);
     if (e == hipSuccess) e = hipMalloc((void**)&p->d_items, sizeof(work_item) * p->cap_items);
-    if (e == hipSuccess) e = hipMalloc((void**)&p->d_num, sizeof(uint32_t));
+    if (e == hipSuccess) e = hipMalloc((void**)&p->d_num, 2 * sizeof(uint32_t));
     if (e == hipSuccess) e = hipMalloc((void**)&p->d_accs, sizeof(unsigned long long) * kNumClasses * p->cap_graphs);
     if (e == hipSuccess) e = hipMalloc((void**)&p->d_ctr, sizeof(unsigned int) * 64);
     if (e == hipSuccess)
@@ -122,7 +126,7 @@ hipError_t ensure_capacity(batch_plan* p, uint32_t graphs, uint32_t items, hipSt
     e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return e;
     hipError_t el = batch_launch(p->d_desc, p->d_items, p->d_num, p->d_accs, (uint64_t)kNumClasses * p->cap_graphs,
-                                 p->d_ctr, p->grid, s);
+                                 p->d_ctr, p->grid, p->hub_grid, s);
     hipError_t ec = hipMemcpyAsync(p->h_accs, p->d_accs, sizeof(unsigned long long) * kNumClasses * p->cap_graphs,
                                    hipMemcpyDeviceToHost, s);
     e = hipStreamEndCapture(s, &p->graph);
@@ -152,15 +156,19 @@ extern "C" int tc_census_batch(tc_context ctx, const tc_graph* graphs, int32_t c
     std::vector<tc_graph> want(graphs, graphs + count);
     hipError_t e = hipSuccess;
     const bool tri = ctx->tuning.tri != 0;
-    if (!(p->valid && p->graphs == want && p->grid == ctx->tuning.batch_blocks && p->tri == tri)) {
-        std::vector<work_item> items;
+    if (!(p->valid && p->graphs == want && p->grid == ctx->tuning.batch_blocks &&
+          p->hub_grid == ctx->tuning.hub_blocks && p->tri == tri)) {
+        std::vector<work_item> items, rest;
         std::vector<graph_desc> descs(count);
         for (int32_t i = 0; i < count; ++i) {
             const device_graph& g = graphs[i]->g;
             descs[i] = describe(g);
-            append_items(g, (uint32_t)i, tri && g.tri.fwd_ptr, items);
+            append_items(g, (uint32_t)i, tri && g.tri.fwd_ptr, items, rest);
         }
-        e = ensure_capacity(p, (uint32_t)count, (uint32_t)items.size(), ctx->stream, ctx->tuning.batch_blocks);
+        const uint32_t nums[2] = {(uint32_t)items.size(), (uint32_t)(items.size() + rest.size())};
+        items.insert(items.end(), rest.begin(), rest.end());     // hub items first
+        e = ensure_capacity(p, (uint32_t)count, (uint32_t)items.size(), ctx->stream, ctx->tuning.batch_blocks,
+                            ctx->tuning.hub_blocks);
         if (e != hipSuccess) return status_from_hip(e);
         uint32_t nitems = (uint32_t)items.size();
         e = hipMemcpyAsync(p->d_desc, descs.data(), sizeof(graph_desc) * count, hipMemcpyHostToDevice, ctx->stream);
@@ -168,7 +176,7 @@ extern "C" int tc_census_batch(tc_context ctx, const tc_graph* graphs, int32_t c
             e = hipMemcpyAsync(p->d_items, items.data(), sizeof(work_item) * nitems, hipMemcpyHostToDevice,
                                ctx->stream);
         if (e == hipSuccess)
-            e = hipMemcpyAsync(p->d_num, &nitems, sizeof(uint32_t), hipMemcpyHostToDevice, ctx->stream);
+            e = hipMemcpyAsync(p->d_num, nums, sizeof(nums), hipMemcpyHostToDevice, ctx->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);   // host vectors go out of scope
         if (e != hipSuccess) {
             p->valid = false;

@@ -46,11 +46,13 @@ constexpr uint32_t kBatchTotalsPerItem = 4096;   // neighbour entries per totals
 constexpr uint32_t kBatchLanePerItem = 256;   // one dyad per thread of a 256-thread workgroup
 constexpr uint32_t kBatchWavePerItem = 16;    // four wavefronts, four dyads each
 
-// Zeroes accs[0..acc_words) and the 8 work counters, then runs the persistent
-// batch kernel over items[0..*num_items) with `grid` workgroups.
-hipError_t batch_launch(const graph_desc* descs, const work_item* items, const uint32_t* num_items,
+// Zeroes accs[0..acc_words) and 16 work counters, then runs two persistent
+// kernels: the hub kernel over the hub items items[0..nums[0]) with hub_grid
+// workgroups, and the batch kernel over the other items items[nums[0]..nums[1])
+// with `grid` workgroups (nums: 2 words of device memory).
+hipError_t batch_launch(const graph_desc* descs, const work_item* items, const uint32_t* nums,
                         unsigned long long* accs, uint64_t acc_words, unsigned int* counters, uint32_t grid,
-                        hipStream_t s);
+                        uint32_t hub_grid, hipStream_t s);
 
 // Copies the 16-class table into the constant table the batch kernel reads.
 hipError_t census_upload_table();

@@ -899,21 +899,22 @@ __global__ __launch_bounds__(kHubB) __attribute__((amdgpu_waves_per_eu(8, 8))) v
 }
 
 // --------------------------------------------------------------- batch ----
-// One persistent launch over the work items of many resident graphs.  A
-// workgroup takes items one at a time (per-XCD counters); an item is a slice of
-// one graph's bucket, over its dyad records or its forward-list edge records:
-// up to 256 lane-mode records (one per thread), up to 4 * kBatchWavePerItem
-// wave-mode records (wavefront w takes every fourth), one group-mode record,
-// one hub task, or a chunk of the totals pass.  Counts go to per-wavefront
-// bins that are flushed into the graph's 16 accumulators whenever the
-// workgroup moves to another graph.
+// Two persistent launches over the work items of many resident graphs: the
+// hub tasks of every graph (k_census_batch_hub, eight wavefronts per SIMD like
+// the single-graph hub kernel), then the other items (k_census_batch).  A
+// workgroup takes items one at a time (per-XCD counters); an item is a slice
+// of one graph's bucket, over its dyad records or its forward-list edge
+// records: up to 256 lane-mode records (one per thread), up to
+// 4 * kBatchWavePerItem wave-mode records (wavefront w takes every fourth), one
+// group-mode record, one hub task, or a chunk of the totals pass.  Counts go
+// to per-wavefront bins that are flushed into the graph's 16 accumulators
+// whenever the workgroup moves to another graph.
 constexpr int kBatchB = 256;
 constexpr int kBatchWaveTile = 512;
 constexpr int kBatchGroupTile = 2048;
 constexpr int kBatchMergeWords = (4 * 2 * (kBatchWaveTile + 1) > 2 * (kBatchGroupTile + 1))
                                      ? 4 * 2 * (kBatchWaveTile + 1) : 2 * (kBatchGroupTile + 1);
-constexpr int kBatchHubWords = (int)kHubLdsWords;
-constexpr int kBatchTileWords = kBatchMergeWords > kBatchHubWords ? kBatchMergeWords : kBatchHubWords;
+constexpr int kBatchTileWords = kBatchMergeWords;
 static_assert(kBatchTotalsPerItem % kBatchB == 0, "totals items are whole steps of the workgroup");
 static_assert(kBatchB == kLaneB, "the slot helpers assume 256-lane workgroups");
 static_assert(2 * kTotalsSlots * kBatchB <= kBatchTileWords, "per-lane slots fit in the tile area");
@@ -944,16 +945,61 @@ __device__ inline void batch_item(uint32_t kind, const work_item& it, const grap
         merge_path<kBatchB, kBatchGroupTile, block_sync, Tri>(r, nbr, tiles, tiles + kBatchGroupTile + 1, &s_xt[0],
                                                               tid, T, h);
         if (!Tri && tid == 0) add_totals(r, t, g.n, T, h);
-    } else {
-        const hub_lds S = hub_carve(tiles);
-        const hub_task* tasks = Tri ? g.edge_tasks : g.hub_tasks;
-        hub_bins_clear(S);
-        uint32_t since = 0;
-        for (uint32_t k = it.begin; k < it.end; ++k) {
-            hub_task_run<Tri>(tasks[k], recs, nbr, g.tpre, g.n, 0u, 0xffffffffu, S, T, h, since);
+    }
+}
+
+__global__ __launch_bounds__(kHubB) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_census_batch_hub(
+    const graph_desc* __restrict__ G, const work_item* __restrict__ items, const uint32_t* __restrict__ nums,
+    unsigned long long* __restrict__ accs, unsigned int* __restrict__ ctr) {
+    __shared__ __attribute__((aligned(16))) uint32_t hub_words[kHubLdsWords];
+    __shared__ unsigned long long bins[wave_bins<kHubB>::kWords];
+    __shared__ uint8_t T[64];
+    __shared__ uint32_t s_next;
+    if (threadIdx.x < 64) T[threadIdx.x] = c_table[threadIdx.x];
+    wave_bins<kHubB> h{bins};
+    h.clear();
+    const hub_lds S = hub_carve(hub_words);
+    hub_bins_clear(S);
+    __syncthreads();
+    const uint32_t count = nums[0];
+    const uint32_t xcd = blockIdx.x % kXcds;
+    uint32_t cur = 0xffffffffu, since = 0;
+    bool cur_tri = false;
+    if (threadIdx.x == 0) s_next = take_chunk(ctr, xcd);
+    __syncthreads();
+    uint32_t idx = s_next;
+    __syncthreads();
+    while (idx < count) {
+        if (threadIdx.x == 0) s_next = take_chunk(ctr, xcd);
+        const work_item it = items[idx];
+        if (it.graph != cur) {
+            if (cur != 0xffffffffu) {
+                if (cur_tri) hub_bins_flush<true>(S, T, h);
+                else hub_bins_flush<false>(S, T, h);
+                h.flush(accs + (uint64_t)kNumClasses * cur);
+                __syncthreads();
+                h.clear();
+            }
+            cur = it.graph;
+            cur_tri = (it.kind & kItemTri) != 0;   // one path per graph
+            since = 0;
             __syncthreads();
         }
-        hub_bins_flush<Tri>(S, T, h);
+        const graph_desc g = G[it.graph];
+        for (uint32_t k = it.begin; k < it.end; ++k) {
+            if (cur_tri)
+                hub_task_run<true>(g.edge_tasks[k], g.edges, g.fwd, g.tpre, g.n, 0u, 0xffffffffu, S, T, h, since);
+            else
+                hub_task_run<false>(g.hub_tasks[k], g.dyads, g.nbr, g.tpre, g.n, 0u, 0xffffffffu, S, T, h, since);
+            __syncthreads();
+        }
+        idx = s_next;
+        __syncthreads();
+    }
+    if (cur != 0xffffffffu) {
+        if (cur_tri) hub_bins_flush<true>(S, T, h);
+        else hub_bins_flush<false>(S, T, h);
+        h.flush(accs + (uint64_t)kNumClasses * cur);
     }
 }
 
@@ -971,16 +1017,16 @@ __global__ __launch_bounds__(kBatchB) void k_census_batch(const graph_desc* __re
     if (threadIdx.x == 0) s_nslots = totals_slots(T, TS, bin_of_slot);
     wave_bins<kBatchB> h{bins};
     h.clear();
-    const uint32_t count = *num_items;
+    const uint32_t first = num_items[0], count = num_items[1];
     const uint32_t xcd = blockIdx.x % kXcds;
     const uint32_t tid = threadIdx.x;
     uint32_t cur = 0xffffffffu;
-    if (tid == 0) s_next = take_chunk(ctr, xcd);
+    if (tid == 0) s_next = first + take_chunk(ctr, xcd);
     __syncthreads();
     uint32_t idx = s_next;
     __syncthreads();
     while (idx < count) {
-        if (tid == 0) s_next = take_chunk(ctr, xcd);
+        if (tid == 0) s_next = first + take_chunk(ctr, xcd);
         const work_item it = items[idx];
         if (it.graph != cur) {
             if (cur != 0xffffffffu) {
@@ -1036,13 +1082,14 @@ __global__ void k_zero_u64(unsigned long long* p, int n) {
 
 }  // namespace
 
-hipError_t batch_launch(const graph_desc* descs, const work_item* items, const uint32_t* num_items,
+hipError_t batch_launch(const graph_desc* descs, const work_item* items, const uint32_t* nums,
                         unsigned long long* accs, uint64_t acc_words, unsigned int* counters, uint32_t grid,
-                        hipStream_t s) {
+                        uint32_t hub_grid, hipStream_t s) {
     uint32_t zb = (uint32_t)std::min<uint64_t>((acc_words + 255) / 256, 1024);
     hipLaunchKernelGGL(k_fill_u64_grid, dim3(zb ? zb : 1), dim3(256), 0, s, accs, acc_words);
-    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, counters, kXcds);
-    hipLaunchKernelGGL(k_census_batch, dim3(grid), dim3(kBatchB), 0, s, descs, items, num_items, accs, counters);
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, counters, 2 * kXcds);
+    hipLaunchKernelGGL(k_census_batch_hub, dim3(hub_grid), dim3(kHubB), 0, s, descs, items, nums, accs, counters);
+    hipLaunchKernelGGL(k_census_batch, dim3(grid), dim3(kBatchB), 0, s, descs, items, nums, accs, counters + kXcds);
     return hipGetLastError();
 }
 

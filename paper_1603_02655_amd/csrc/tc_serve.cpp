@@ -83,12 +83,12 @@ hipError_t slot_reserve(slot& s, uint32_t graphs, uint32_t items) {
     s.cap_items = std::max<uint32_t>(items + items / 2, 4096);
     hipError_t e = hipMalloc((void**)&s.d_desc, sizeof(graph_desc) * s.cap_graphs);
     if (e == hipSuccess) e = hipMalloc((void**)&s.d_items, sizeof(work_item) * s.cap_items);
-    if (e == hipSuccess) e = hipMalloc((void**)&s.d_num, sizeof(uint32_t));
+    if (e == hipSuccess) e = hipMalloc((void**)&s.d_num, 2 * sizeof(uint32_t));
     if (e == hipSuccess) e = hipMalloc((void**)&s.d_accs, sizeof(unsigned long long) * kNumClasses * s.cap_graphs);
     if (e == hipSuccess) e = hipMalloc((void**)&s.d_ctr, sizeof(unsigned int) * 64);
     if (e == hipSuccess) e = hipHostMalloc((void**)&s.h_desc, sizeof(graph_desc) * s.cap_graphs);
     if (e == hipSuccess) e = hipHostMalloc((void**)&s.h_items, sizeof(work_item) * s.cap_items);
-    if (e == hipSuccess) e = hipHostMalloc((void**)&s.h_num, sizeof(uint32_t));
+    if (e == hipSuccess) e = hipHostMalloc((void**)&s.h_num, 2 * sizeof(uint32_t));
     if (e == hipSuccess) e = hipHostMalloc((void**)&s.h_accs, sizeof(unsigned long long) * kNumClasses * s.cap_graphs);
     if (e != hipSuccess) slot_free(s);
     return e;
@@ -98,10 +98,14 @@ hipError_t slot_reserve(slot& s, uint32_t graphs, uint32_t items) {
 uint64_t job_footprint(const job& j) {
     uint64_t ws = sizeof(unsigned long long) * kNumClasses + sizeof(graph_desc);
     if (!j.cold) {
+        // the items append_items makes for the graph (forward-list items when it has forward lists)
         const device_graph& g = j.g->g;
-        uint64_t items = g.n_hub_tasks + (g.bucket_off[3] - g.bucket_off[2]) +
-                         (g.bucket_off[2] - g.bucket_off[1] + kBatchWavePerItem - 1) / kBatchWavePerItem +
-                         (g.bucket_off[1] - g.bucket_off[0] + kBatchLanePerItem - 1) / kBatchLanePerItem;
+        const bool tri = g.tri.fwd_ptr != nullptr;
+        const uint64_t* off = tri ? g.tri.edges.off : g.bucket_off;
+        uint64_t items = (tri ? g.tri.edges.n_tasks : g.n_hub_tasks) + (off[3] - off[2]) +
+                         (off[2] - off[1] + kBatchWavePerItem - 1) / kBatchWavePerItem +
+                         (off[1] - off[0] + kBatchLanePerItem - 1) / kBatchLanePerItem;
+        if (tri) items += (g.U + kBatchTotalsPerItem - 1) / kBatchTotalsPerItem;
         return ws + sizeof(work_item) * items;
     }
     uint64_t m = j.src.size();
@@ -202,7 +206,7 @@ bool launch_round(serve_state* S, int si) {
         std::vector<int32_t>().swap(j->src);
         std::vector<int32_t>().swap(j->dst);
     }
-    std::vector<work_item> items;
+    std::vector<work_item> items, rest;
     std::vector<graph_desc> descs(s.jobs.size());
     for (size_t i = 0; i < s.jobs.size(); ++i) {
         job* j = s.jobs[i];
@@ -212,21 +216,25 @@ bool launch_round(serve_state* S, int si) {
         }
         const device_graph& g = j->cold ? j->built : j->g->g;
         descs[i] = describe(g);
-        append_items(g, (uint32_t)i, ctx->tuning.tri && g.tri.fwd_ptr, items);
+        append_items(g, (uint32_t)i, ctx->tuning.tri && g.tri.fwd_ptr, items, rest);
     }
+    const uint32_t n_hub = (uint32_t)items.size();
+    items.insert(items.end(), rest.begin(), rest.end());     // hub items first
     hipError_t e = slot_reserve(s, (uint32_t)s.jobs.size(), (uint32_t)items.size());
     if (e == hipSuccess) {
         std::memcpy(s.h_desc, descs.data(), sizeof(graph_desc) * descs.size());
         if (!items.empty()) std::memcpy(s.h_items, items.data(), sizeof(work_item) * items.size());
-        *s.h_num = (uint32_t)items.size();
+        s.h_num[0] = n_hub;
+        s.h_num[1] = (uint32_t)items.size();
         e = hipMemcpyAsync(s.d_desc, s.h_desc, sizeof(graph_desc) * descs.size(), hipMemcpyHostToDevice, s.stream);
         if (e == hipSuccess && !items.empty())
             e = hipMemcpyAsync(s.d_items, s.h_items, sizeof(work_item) * items.size(), hipMemcpyHostToDevice,
                                s.stream);
-        if (e == hipSuccess) e = hipMemcpyAsync(s.d_num, s.h_num, sizeof(uint32_t), hipMemcpyHostToDevice, s.stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(s.d_num, s.h_num, 2 * sizeof(uint32_t), hipMemcpyHostToDevice, s.stream);
         if (e == hipSuccess)
             e = batch_launch(s.d_desc, s.d_items, s.d_num, s.d_accs, (uint64_t)kNumClasses * s.jobs.size(), s.d_ctr,
-                             ctx->tuning.batch_blocks, s.stream);
+                             ctx->tuning.batch_blocks, ctx->tuning.hub_blocks, s.stream);
         if (e == hipSuccess)
             e = hipMemcpyAsync(s.h_accs, s.d_accs, sizeof(unsigned long long) * kNumClasses * s.jobs.size(),
                                hipMemcpyDeviceToHost, s.stream);

@@ -25,6 +25,10 @@ double now_ms() {
 
 constexpr int kSlots = 3;                 // rounds in flight
 constexpr size_t kMaxJobsPerRound = 512;
+// A round closes once its jobs hold this many neighbour entries (about 5 ms of
+// census at the batched rate): rounds stay short, so a request admitted behind
+// a full queue waits for a few short rounds instead of one long one.
+constexpr uint64_t kMaxRoundEntries = 64ull << 20;
 
 enum job_state { kQueued, kRunning, kDone };
 
@@ -37,6 +41,7 @@ struct job {
     std::vector<int32_t> src, dst;
     device_graph built;                   // a cold job's graph, freed when the round ends
     uint64_t footprint = 0;
+    uint64_t entries = 0;                 // neighbour entries (2 x dyads; 2 x arcs for a cold job)
     double t_submit = 0, t_admit = 0, t_done = 0;
     int status = TC_OK;
     job_state state = kQueued;
@@ -268,7 +273,9 @@ void worker_main(serve_state* S) {
         if (free_slot >= 0 && !S->queue.empty()) {
             slot& s = S->slots[free_slot];
             const double t = now_ms();
-            while (!S->queue.empty() && s.jobs.size() < kMaxJobsPerRound) {
+            uint64_t round_entries = 0;
+            while (!S->queue.empty() && s.jobs.size() < kMaxJobsPerRound &&
+                   (s.jobs.empty() || round_entries + S->queue.front()->entries <= kMaxRoundEntries)) {
                 job* j = S->queue.front();
                 if (j->footprint > S->ctx->budget) {          // can never fit
                     S->queue.pop_front();
@@ -282,6 +289,7 @@ void worker_main(serve_state* S) {
                 if (S->bytes_in_flight + j->footprint > S->ctx->budget) break;   // wait for memory
                 S->queue.pop_front();
                 S->bytes_in_flight += j->footprint;
+                round_entries += j->entries;
                 j->state = kRunning;
                 j->t_admit = t;
                 S->admission_ms_sum += t - j->t_submit;
@@ -395,6 +403,7 @@ int submit_job(tc_context ctx, job* j, tc_ticket* out) {
         return rc;
     }
     j->footprint = job_footprint(*j);
+    j->entries = j->cold ? 2 * (uint64_t)j->src.size() : j->g->g.U;
     {
         std::lock_guard<std::mutex> lk(S->mu);
         if (S->stop) {

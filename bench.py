@@ -33,14 +33,19 @@ def log(*a):
 
 
 def census_source_hash() -> str:
-    """sha256 (first 16 hex digits) of the library sources, in name order: a
-    counter summary taken on other sources no longer describes the kernels."""
+    """sha256 (first 16 hex digits) of the library's code (sources in name
+    order, comments and whitespace removed): a counter summary taken on other
+    code no longer describes the kernels."""
+    import re
     d = os.path.join(ROOT, "paper_1603_02655_amd", "csrc")
     h = hashlib.sha256()
     for name in sorted(os.listdir(d)):
         if name.endswith((".hip", ".h", ".cpp")):
-            with open(os.path.join(d, name), "rb") as f:
-                h.update(name.encode() + b"\0" + f.read())
+            with open(os.path.join(d, name)) as f:
+                text = f.read()
+            text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+            text = re.sub(r"//[^\n]*", " ", text)
+            h.update(name.encode() + b"\0" + " ".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 

@@ -16,13 +16,21 @@
 // N(u) and N(v) only has to find the shared vertices, each of which moves one
 // count from its single-list class to its full-code class.
 //
-// Three execution modes over the degree buckets (key |N(u)| + |N(v)| - 2):
-//   lane  : one lane per dyad, two-pointer merge of the two rows;
-//   wave  : one 64-lane wavefront per dyad, merge path over LDS-staged tiles;
-//   group : one 256-lane workgroup per dyad, merge path over larger tiles.
-// Counts accumulate in 64-bit LDS bins (private per lane in the lane mode, per
-// wavefront elsewhere); each workgroup adds its 16 sums to the graph's
-// accumulators with one 64-bit global atomic per class when it finishes.
+// Four execution modes over the buckets (key |N(u)| + |N(v)| - 2, and the
+// longer row for the hub bucket):
+//   lane  : one lane per record, the two rows compared 8 entries at a time;
+//   wave  : one 64-lane wavefront per record, merge path over LDS-staged tiles;
+//   group : one 256-lane workgroup per record, merge path over larger tiles;
+//   hub   : one workgroup per run of records that share an endpoint (anchor),
+//           whose row is staged in an LDS hash table and probed by the other
+//           rows.
+// The same kernels run over the dyad records (Tri = false) or over the
+// forward-list edge records (Tri = true), where a shared vertex closes a
+// triangle that is credited to its three dyads (on_triangle) and the per-dyad
+// terms come from a separate pass over the neighbour entries (k_census_totals).
+// Counts accumulate in LDS bins (per lane, per wavefront, or per signature in
+// the hub mode); each workgroup adds its 16 sums to the graph's accumulators
+// with one 64-bit global atomic per class when it finishes.
 //
 // The class of every code comes from a 64-entry table staged in LDS.  The
 // single-graph kernels take the table as an argument: the 16-class table, or
@@ -169,8 +177,8 @@ __device__ inline dyad_rec load_rec(const dyad_rec* p) {
 constexpr uint32_t kSentinel = 0xffffffffu;
 
 // ---------------------------------------------------------------- lane ----
-// One lane per dyad: a two-pointer merge of rows u and v read from global
-// memory (L1/L2 resident for the short rows of this bucket).
+// One lane per record: the two rows, read from global memory (L1/L2 resident
+// for the short rows of this bucket), compared in chunks.
 constexpr int kLaneB = 256;
 
 // The two rows are compared kLaneChunk entries at a time: a chunk of each is
@@ -261,8 +269,9 @@ __global__ __launch_bounds__(kLaneB) void k_census_lane(census_args L) {
 // u for the dyad (y, x).  The dyadic base n - |N(u)| - |N(v)| is split the
 // same way: n - |N(x)| from the first side, -|N(x)| from the second.  Every
 // read is coalesced (the row of an entry is shared by its neighbours).
-// Entries base + k * B + threadIdx.x (k < kPer) below `end`, their loads
-// issued before any is used.
+//
+// totals_entries: entries base + k * B + threadIdx.x (k < kPer) below `end`,
+// their loads issued before any is used.
 template <uint32_t kPer, uint32_t B, class H>
 __device__ inline void totals_entries(uint64_t base, uint64_t end, const uint32_t* __restrict__ nbr,
                                       const uint32_t* __restrict__ owner, const int64_t* __restrict__ row_ptr,
@@ -304,16 +313,16 @@ __device__ inline void totals_entries(uint64_t base, uint64_t end, const uint32_
 constexpr uint32_t kTotalsPer = 4;   // entries per thread and step
 constexpr uint32_t kTotalsSlots = 8; // distinct bins the totals pass can reach (any table here has <= 8)
 
-// Per-lane bins over a few slots: the totals pass reaches only the bins of the
-// codes f, f | t << 2 and f | t << 4 (f, t in 1..3), at most kTotalsSlots of
-// them, so a lane keeps one 64-bit slot per reachable bin (16 KB of LDS for
-// 256 lanes instead of 35 KB).  The codes are remapped to slots in a table.
 // Adds straight to a graph's 16 accumulators in global memory.
 struct global_bins {
     unsigned long long* acc;
     __device__ inline void add(uint32_t cls, unsigned long long x) { atomicAdd(&acc[cls], x); }
 };
 
+// Per-lane bins over a few slots: the totals pass reaches only the bins of the
+// codes f, f | t << 2 and f | t << 4 (f, t in 1..3), at most kTotalsSlots of
+// them, so a lane keeps one 64-bit slot per reachable bin (16 KB of LDS for
+// 256 lanes instead of 35 KB).  The codes are remapped to slots in a table.
 struct slot_bins {
     unsigned long long* bins;   // kTotalsSlots x kLaneB
     __device__ inline void add(uint32_t slot, unsigned long long x) {
@@ -560,14 +569,14 @@ __global__ __launch_bounds__(kGroupB) void k_census_group(census_args L, unsigne
 
 
 // ----------------------------------------------------------------- hub ----
-// Hub dyads, grouped by anchor (their endpoint of larger degree).  A
-// workgroup takes one hub task (up to kHubChunk dyads that share the anchor),
-// stages the anchor's row tile by tile into an LDS hash table (kHubTile
-// entries in kHubSlots slots, linear probing), and streams the other
-// endpoint's row of every dyad of the task against it: each entry of that row
-// is probed once, in the tile whose vertex range holds it.  The anchor row is
-// thus read once per task instead of once per dyad, and the work per dyad is
-// proportional to the smaller degree.
+// Hub records, grouped by anchor (their endpoint with the longer row).  A
+// workgroup takes one hub task (up to kHubChunk records that share the
+// anchor), stages the anchor's row tile by tile into an LDS hash table
+// (kHubTile entries in 4-slot buckets, the next bucket on overflow), and
+// streams the other endpoint's row of every record of the task against it:
+// each entry of that row is probed once, in the tile whose vertex range holds
+// it.  The anchor row is thus read once per task instead of once per record,
+// and the work per record is proportional to the shorter row.
 constexpr int kHubB = 256;
 constexpr uint32_t kHubTile = kHubTileEntries;
 constexpr uint32_t kHubBuckets = kHubTile / 2;           // buckets of 4 slots, mean load 2 entries

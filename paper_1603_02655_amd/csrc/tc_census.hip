@@ -598,6 +598,10 @@ __device__ inline uint32_t find_first_ge(const uint32_t* __restrict__ nbr, uint3
 
 __device__ inline uint32_t hub_bucket(uint32_t w) { return (w * 0x9E3779B1u) >> (32 - kHubBucketBits); }
 
+// Bit of a vertex in the tile's filter (another multiplier than the buckets').
+constexpr uint32_t kHubFilterShift = 32 - 14;
+__device__ inline uint32_t hub_filter_bit(uint32_t w) { return (w * 0x85EBCA6Bu) >> kHubFilterShift; }
+
 // Buckets fill their slots in order, so a bucket whose last slot is empty
 // ends the probe sequence of every vertex that hashes to it or before it.
 __device__ inline void hub_insert(uint32_t* hash, uint32_t e) {
@@ -691,8 +695,11 @@ struct hub_lds {
     uint32_t* off;    // probes of this tile, then their exclusive scan (kHubChunk + 1)
     uint32_t* wsum;   // 4 words
     uint32_t* sig;    // kSigs x (kHubB / 64)
+    uint32_t* filt;   // kHubFilterBits bits: a vertex whose bit is clear is not in the tile
 };
-constexpr uint32_t kHubLdsWords = kHubSlots + 2 * kHubChunk + (kHubChunk + 4) + 4 + kSigs * (kHubB / 64);
+constexpr uint32_t kHubFilterBits = 1u << (32 - kHubFilterShift);
+constexpr uint32_t kHubLdsWords =
+    kHubSlots + 2 * kHubChunk + (kHubChunk + 4) + 4 + kSigs * (kHubB / 64) + kHubFilterBits / 32;
 
 __device__ inline hub_lds hub_carve(uint32_t* base) {
     uint32_t* p = base;
@@ -702,7 +709,8 @@ __device__ inline hub_lds hub_carve(uint32_t* base) {
     S.meta = p;  p += kHubChunk;
     S.off = p;   p += kHubChunk + 4;
     S.wsum = p;  p += 4;
-    S.sig = p;
+    S.sig = p;   p += kSigs * (kHubB / 64);
+    S.filt = p;
     return S;
 }
 
@@ -760,8 +768,13 @@ __device__ inline void hub_task_run(const hub_task& tk, const dyad_rec* __restri
     for (uint32_t tb = hb; tb < he; tb += kHubTile) {
         const uint32_t te = min(he, tb + kHubTile);
         for (uint32_t k = tid; k < kHubSlots; k += kHubB) S.hash[k] = kEmpty;
+        for (uint32_t k = tid; k < kHubFilterBits / 32; k += kHubB) S.filt[k] = 0;
         __syncthreads();
-        for (uint32_t k = tb + tid; k < te; k += kHubB) hub_insert(S.hash, nbr[k]);
+        for (uint32_t k = tb + tid; k < te; k += kHubB) {
+            hub_insert(S.hash, nbr[k]);
+            const uint32_t fb = hub_filter_bit(nbr[k] >> 2);
+            atomicOr(&S.filt[fb >> 5], 1u << (fb & 31u));
+        }
         if (multi_tile) {
             const uint32_t w_end = te < he ? (nbr[te] >> 2) : kEmpty;
             for (uint32_t i = tid; i < nrec; i += kHubB) {
@@ -852,7 +865,11 @@ __device__ inline void hub_task_run(const hub_task& tk, const dyad_rec* __restri
                 }
 #pragma unroll
                 for (uint32_t k = 0; k < kHubGather; ++k) {
-                    const uint32_t hit = e[k] != kEmpty ? hub_probe(S.hash, e[k] >> 2) : kEmpty;
+                    uint32_t hit = kEmpty;
+                    if (e[k] != kEmpty) {
+                        const uint32_t fb = hub_filter_bit(e[k] >> 2);
+                        if ((S.filt[fb >> 5] >> (fb & 31u)) & 1u) hit = hub_probe(S.hash, e[k] >> 2);
+                    }
                     const bool miss = hit == kEmpty;
                     const uint32_t x = mk[k] >> 3, fuv = mk[k] & 3u;
                     const bool anchor_u = (mk[k] & 4u) != 0;

@@ -355,3 +355,54 @@ def test_citation_full_vs_oracle(ctx):
         say("[gpu] oracle MT on citation")
         want = og.census_mt(min(16, os.cpu_count() or 1))
     assert got.tolist() == want.tolist()
+
+
+# ------------------------------------------- forward lists longer than a tile ----
+
+def _modes_agree(ctx, n, src, dst, modes):
+    out = {}
+    for mode in modes:
+        say(f"[gpu] long forward lists n={n} m={len(src)} mode={mode}")
+        got, info = gpu_census(ctx, n, src, dst, mode)
+        out[mode] = got
+    first = next(iter(out.values()))
+    for mode, got in out.items():
+        assert got.tolist() == first.tolist(), mode
+    return first
+
+
+def test_forward_lists_longer_than_a_tile(ctx):
+    # degree ties are broken by id, so in a complete digraph N+(x) holds the
+    # n - 1 - x vertices above x: the first vertices' forward lists span two
+    # LDS tiles of the hub mode (1024 entries)
+    n = 1100
+    idx = np.arange(n, dtype=np.int32)
+    src = np.repeat(idx, n)
+    dst = np.tile(idx, n)
+    keep = src != dst
+    got = _modes_agree(ctx, n, src[keep], dst[keep], ["default", "tri-hub", "hub"])
+    want = np.zeros(16, np.uint64)
+    want[triads.INDEX["300"]] = comb(n, 3)
+    assert got.tolist() == want.tolist()
+    # random tournament: 030T = sum over v of C(out(v), 2), the rest 030C
+    rng = np.random.default_rng(1100)
+    a, b = np.triu_indices(n, 1)
+    flip = rng.random(a.size) < 0.5
+    s, d = np.where(flip, b, a).astype(np.int32), np.where(flip, a, b).astype(np.int32)
+    got = _modes_agree(ctx, n, s, d, ["default", "tri-hub", "hub", "group"])
+    outdeg = np.bincount(s, minlength=n)
+    t030 = sum(comb(int(k), 2) for k in outdeg)
+    want = np.zeros(16, np.uint64)
+    want[triads.INDEX["030T"]] = t030
+    want[triads.INDEX["030C"]] = comb(n, 3) - t030
+    assert got.tolist() == want.tolist()
+
+
+def test_dense_digraph_identities_across_modes(ctx):
+    n = 1100
+    rng = np.random.default_rng(1101)
+    mat = rng.random((n, n)) < 0.75
+    np.fill_diagonal(mat, False)
+    src, dst = (x.astype(np.int32) for x in np.nonzero(mat))
+    got = _modes_agree(ctx, n, src, dst, ["default", "tri-hub", "tri-lane", "hub", "lane"])
+    assert triads.identity_violations(n, src, dst, got) == []

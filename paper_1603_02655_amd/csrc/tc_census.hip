@@ -585,7 +585,7 @@ constexpr int kHubBucketBits = __builtin_ctz(kHubBuckets);
 static_assert((kHubBuckets & (kHubBuckets - 1)) == 0, "power-of-two bucket count");
 constexpr uint32_t kEmpty = 0xffffffffu;                 // never an entry (w < 2^23)
 constexpr uint32_t kHubGather = 8;
-constexpr uint32_t kHubFlushAfter = 1u << 25;             // probes per lane between histogram flushes
+constexpr uint32_t kHubFlushAfter = (1u << 24) - 1u;      // kHubB times this stays below 2^32
 
 // First position in [lo, hi) of a sorted row whose vertex is >= w.
 __device__ inline uint32_t find_first_ge(const uint32_t* __restrict__ nbr, uint32_t lo, uint32_t hi, uint32_t w) {
@@ -599,7 +599,7 @@ __device__ inline uint32_t find_first_ge(const uint32_t* __restrict__ nbr, uint3
 __device__ inline uint32_t hub_bucket(uint32_t w) { return (w * 0x9E3779B1u) >> (32 - kHubBucketBits); }
 
 // Bit of a vertex in the tile's filter (another multiplier than the buckets').
-constexpr uint32_t kHubFilterShift = 32 - 14;
+constexpr uint32_t kHubFilterShift = 32 - 13;
 __device__ inline uint32_t hub_filter_bit(uint32_t w) { return (w * 0x85EBCA6Bu) >> kHubFilterShift; }
 
 // Buckets fill their slots in order, so a bucket whose last slot is empty
@@ -686,49 +686,50 @@ struct scaled_bins {
     __device__ inline void add(uint32_t cls, unsigned long long x) { h.add(cls, x * c); }
 };
 
-// LDS of the hub mode: the hash table, three per-dyad arrays, scan scratch and
-// the per-wavefront signature histograms.
+// LDS of the hub mode: the hash table, one candidate ring per wavefront, three
+// per-dyad arrays, scan scratch, the signature histogram and the filter.
+constexpr uint32_t kHubRing = 128;   // candidates a wavefront holds between probe rounds
 struct hub_lds {
     uint32_t* hash;   // kHubSlots, 16-byte aligned
+    uint2* ring;      // kHubRing x (kHubB / 64) candidates: (entry, meta word of its record)
     uint32_t* pos;    // next unprobed position in the other endpoint's row
     uint32_t* meta;   // (x << 3) | (anchor is u) << 2 | f_uv
     uint32_t* off;    // probes of this tile, then their exclusive scan (kHubChunk + 1)
     uint32_t* wsum;   // 4 words
-    uint32_t* sig;    // kSigs x (kHubB / 64)
+    uint32_t* sig;    // kSigs counts shared by the workgroup
     uint32_t* filt;   // kHubFilterBits bits: a vertex whose bit is clear is not in the tile
 };
 constexpr uint32_t kHubFilterBits = 1u << (32 - kHubFilterShift);
-constexpr uint32_t kHubLdsWords =
-    kHubSlots + 2 * kHubChunk + (kHubChunk + 4) + 4 + kSigs * (kHubB / 64) + kHubFilterBits / 32;
+constexpr uint32_t kHubLdsWords = kHubSlots + 2 * kHubRing * (kHubB / 64) + 2 * kHubChunk + (kHubChunk + 4) + 4 +
+                                  kSigs + kHubFilterBits / 32;
 
 __device__ inline hub_lds hub_carve(uint32_t* base) {
     uint32_t* p = base;
     hub_lds S;
     S.hash = p;  p += kHubSlots;
+    S.ring = reinterpret_cast<uint2*>(p);  p += 2 * kHubRing * (kHubB / 64);
     S.pos = p;   p += kHubChunk;
     S.meta = p;  p += kHubChunk;
     S.off = p;   p += kHubChunk + 4;
     S.wsum = p;  p += 4;
-    S.sig = p;   p += kSigs * (kHubB / 64);
+    S.sig = p;   p += kSigs;
     S.filt = p;
     return S;
 }
 
 __device__ inline void hub_bins_clear(const hub_lds& S) {
-    for (uint32_t k = threadIdx.x; k < kSigs * (kHubB / 64); k += kHubB) S.sig[k] = 0;
+    for (uint32_t k = threadIdx.x; k < kSigs; k += kHubB) S.sig[k] = 0;
 }
 
-// Adds the signature counts to h (one thread per wavefront and signature) and
-// clears them.
+// Adds the signature counts to h (one thread per signature) and clears them.
 template <bool Tri, class H>
 __device__ inline void hub_bins_flush(const hub_lds& S, const uint8_t* T, H& h) {
     __syncthreads();
-    for (uint32_t k = threadIdx.x; k < kSigs * (kHubB / 64); k += kHubB) {
+    for (uint32_t k = threadIdx.x; k < kSigs; k += kHubB) {
         const uint32_t c = S.sig[k];
         if (c == 0) continue;
         S.sig[k] = 0;
-        const uint32_t s = k % kSigs;
-        const uint32_t f = 1u + s % 3u, fa = 1u + (s / 3u) % 3u, fb = 1u + (s / 9u) % 3u, where = s / 27u;
+        const uint32_t f = 1u + k % 3u, fa = 1u + (k / 3u) % 3u, fb = 1u + (k / 9u) % 3u, where = k / 27u;
         // ids that put w below u, between u and v, or above v
         const uint32_t u = 1u, v = 3u, w = where * 2u;
         scaled_bins<H> sh{h, (unsigned long long)c};
@@ -741,8 +742,9 @@ __device__ inline void hub_bins_flush(const hub_lds& S, const uint8_t* T, H& h) 
 // anchor row: clear and fill the hash table; count, for every dyad, the
 // entries of the other row that fall in the tile's vertex range; scan the
 // counts; then each wavefront probes a quarter of the flattened (dyad, entry)
-// list, 64 adjacent entries per gather and kHubGather gathers in flight.  A hit
-// adds one to its wavefront's count of the hit's signature.
+// list, 64 adjacent entries per gather and kHubGather gathers in flight, and
+// probes the entries that pass the tile's filter 64 at a time.  A hit adds one
+// to the workgroup's count of the hit's signature.
 template <bool Tri, class H>
 __device__ inline void hub_task_run(const hub_task& tk, const dyad_rec* __restrict__ dyads,
                                     const uint32_t* __restrict__ nbr, const uint64_t* __restrict__ tpre, uint64_t n,
@@ -750,7 +752,6 @@ __device__ inline void hub_task_run(const hub_task& tk, const dyad_rec* __restri
                                     uint32_t& since) {
     const uint32_t tid = threadIdx.x;
     const uint32_t nrec = tk.end - tk.begin, a = tk.anchor;
-    uint32_t* my_sig = S.sig + (tid >> 6) * kSigs;
     const dyad_rec r0 = load_rec(dyads + tk.begin);
     const uint32_t hb = r0.u == a ? r0.bu : r0.bv, he = r0.u == a ? r0.eu : r0.ev;
     const bool multi_tile = he - hb > kHubTile;
@@ -791,21 +792,53 @@ __device__ inline void hub_task_run(const hub_task& tk, const dyad_rec* __restri
         __syncthreads();
         block_scan_u32(S.off, nrec, S.wsum);
         const uint32_t P = S.off[nrec];
+        // The shared 32-bit signature counts grow by at most P in this tile:
+        // they are flushed first when the tiles since the last flush could
+        // take them past 2^32 (`per` is the same on every thread).
+        const uint32_t per = (P + kHubB - 1) / kHubB;
+        if (since + per > kHubFlushAfter) {
+            hub_bins_flush<Tri>(S, T, h);
+            since = 0;
+        }
+        since += per;
         // Wavefront w takes the w-th quarter [q0, q1) of the flattened list and
-        // walks it in windows of 64 * kHubGather entries; lane l takes the
-        // kHubGather consecutive entries at l * kHubGather of each window, so a
-        // wavefront's gathers stay within 64 * kHubGather adjacent words.  A
-        // lane keeps the record of its current entry and, prefetched, the
-        // start, position and meta word of the record after it: moving to the
-        // next record waits on no LDS read.
+        // walks it in windows of 64 * kHubGather entries; lane l takes entries
+        // l, l + 64, ... of each window, so every gather reads 64 adjacent
+        // entries (a few cache lines).  A lane keeps the record of its current
+        // entry and, prefetched, the start, position and meta word of the
+        // record after it: moving to the next record waits on no LDS read.
+        // Entries that pass the filter are appended to the wavefront's ring of
+        // candidates, and every 64 candidates are probed together, one per lane.
         const uint32_t lane = tid & 63u, wid = tid >> 6;
         constexpr uint32_t kWaves = kHubB / 64;
         const uint32_t q0 = (uint32_t)(((uint64_t)P * wid) / kWaves), q1 = (uint32_t)(((uint64_t)P * (wid + 1)) / kWaves);
-        const uint32_t per = (P + kHubB - 1) / kHubB + kHubGather;   // bound on a lane's probes in this tile
-        if (q0 + kHubGather * lane < q1) {
+        uint2* ring = S.ring + wid * kHubRing;
+        uint32_t head = 0, cnt = 0;   // the same on every lane: ring[head, head + cnt) waits to be probed
+        // Probes ring[head + l] on the lanes l < c (c <= 64): a hit adds one to
+        // the count of its signature.
+        auto probe_round = [&](uint32_t c) {
+            wave_sync{}();
+            if (lane < c) {
+                const uint2 q = ring[(head + lane) & (kHubRing - 1)];
+                const uint32_t w = q.x >> 2;
+                const uint32_t hit = hub_probe(S.hash, w);
+                if (hit != kEmpty) {
+                    const uint32_t x = q.y >> 3, fuv = q.y & 3u;
+                    const bool anchor_u = (q.y & 4u) != 0;
+                    const uint32_t u = anchor_u ? a : x, v = anchor_u ? x : a;
+                    const uint32_t fx = q.x & 3u, fh = hit & 3u;
+                    const uint32_t fa = anchor_u ? fh : fx, fb = anchor_u ? fx : fh;
+                    atomicAdd(&S.sig[shared_sig(w, u, v, fuv, fa, fb)], 1u);
+                }
+            }
+            wave_sync{}();
+            head += c;
+        };
+        if (q0 < q1) {
             uint32_t i = 0;
             {
-                const uint32_t first = q0 + kHubGather * lane;
+                // lanes past the quarter's end take its last record and gather nothing
+                const uint32_t first = min(q0 + lane, q1 - 1u);
                 uint32_t hi = nrec;                     // record holding `first`: off[i] <= first < off[i+1]
                 while (hi - i > 1) {
                     const uint32_t mid = (i + hi) >> 1;
@@ -822,8 +855,13 @@ __device__ inline void hub_task_run(const hub_task& tk, const dyad_rec* __restri
                 const uint32_t o4 = S.off[min(i + 4, nrec)], o5 = S.off[min(i + 5, nrec)];
                 i += 1u + (ff >= o2 ? 1u : 0u) + (ff >= o3 ? 1u : 0u) + (ff >= o4 ? 1u : 0u) + (ff >= o5 ? 1u : 0u);
                 next = S.off[i + 1];
-                while (ff >= next) {
-                    ++i;
+                if (ff >= next) {
+                    // further ahead: the last record starting at or before ff, by bisection
+                    uint32_t hi = nrec;
+                    while (hi - i > 1) {
+                        const uint32_t mid = (i + hi) >> 1;
+                        if (S.off[mid] <= ff) i = mid; else hi = mid;
+                    }
                     next = S.off[i + 1];
                 }
                 base = S.pos[i] - S.off[i];
@@ -833,12 +871,10 @@ __device__ inline void hub_task_run(const hub_task& tk, const dyad_rec* __restri
                 n_m = S.meta[min(i + 1, nrec - 1)];
             };
             for (uint32_t win = q0; win < q1; win += 64u * kHubGather) {
-                const uint32_t g0 = win + kHubGather * lane;
-                if (g0 < q1 && g0 >= next) seek(g0);
                 uint32_t e[kHubGather], mk[kHubGather];
 #pragma unroll
                 for (uint32_t k = 0; k < kHubGather; ++k) {
-                    const uint32_t ff = g0 + k;
+                    const uint32_t ff = win + 64u * k + lane;
                     e[k] = kEmpty;
                     mk[k] = m;
                     if (ff < q1) {
@@ -860,36 +896,42 @@ __device__ inline void hub_task_run(const hub_task& tk, const dyad_rec* __restri
                             }
                         }
                         mk[k] = m;
-                        e[k] = nbr[base + ff];
+                        e[k] = base + ff;       // position in the row array, gathered below
                     }
+                }
+                // every gather of the window in flight together
+#pragma unroll
+                for (uint32_t k = 0; k < kHubGather; ++k) e[k] = e[k] != kEmpty ? nbr[e[k]] : kEmpty;
+                // filter words of all the entries first, then the appends
+                uint32_t fw[kHubGather], pm = 0;
+#pragma unroll
+                for (uint32_t k = 0; k < kHubGather; ++k) fw[k] = S.filt[hub_filter_bit(e[k] >> 2) >> 5];
+#pragma unroll
+                for (uint32_t k = 0; k < kHubGather; ++k) {
+                    const uint32_t fb = hub_filter_bit(e[k] >> 2);
+                    pm |= (e[k] != kEmpty ? (fw[k] >> (fb & 31u)) & 1u : 0u) << k;
                 }
 #pragma unroll
                 for (uint32_t k = 0; k < kHubGather; ++k) {
-                    uint32_t hit = kEmpty;
-                    if (e[k] != kEmpty) {
-                        const uint32_t fb = hub_filter_bit(e[k] >> 2);
-                        if ((S.filt[fb >> 5] >> (fb & 31u)) & 1u) hit = hub_probe(S.hash, e[k] >> 2);
+                    const bool pass = (pm >> k) & 1u;
+                    const unsigned long long bal = __ballot(pass);
+                    if (pass) {
+                        const uint32_t r = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
+                                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+                        ring[(head + cnt + r) & (kHubRing - 1)] = make_uint2(e[k], mk[k]);
                     }
-                    const bool miss = hit == kEmpty;
-                    const uint32_t x = mk[k] >> 3, fuv = mk[k] & 3u;
-                    const bool anchor_u = (mk[k] & 4u) != 0;
-                    const uint32_t u = anchor_u ? a : x, v = anchor_u ? x : a, w = e[k] >> 2;
-                    const uint32_t fx = e[k] & 3u, fh = hit & 3u;
-                    const uint32_t fa = anchor_u ? fh : fx, fb = anchor_u ? fx : fh;
-                    if (!miss) atomicAdd(&my_sig[shared_sig(w, u, v, fuv, fa, fb)], 1u);
+                    cnt += (uint32_t)__popcll(bal);
+                    if (cnt >= 64u) {
+                        probe_round(64u);
+                        cnt -= 64u;
+                    }
                 }
             }
+            if (cnt != 0) probe_round(cnt);
         }
         __syncthreads();
         if (multi_tile)
             for (uint32_t i = tid; i < nrec; i += kHubB) S.pos[i] += S.off[i + 1] - S.off[i];
-        // A wavefront's 32-bit signature counts grow by at most 64 per probe
-        // step: flush them long before 2^32 (`per` is the same on every lane).
-        since += per;
-        if (since >= kHubFlushAfter) {
-            hub_bins_flush<Tri>(S, T, h);
-            since = 0;
-        }
         __syncthreads();
     }
 }

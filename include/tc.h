@@ -74,6 +74,9 @@ typedef struct {
     uint64_t tri_tasks;           /* hub tasks over the forward lists */
     uint64_t tri_stream;          /* sum over hub edges of the non-anchor forward-list length */
     uint64_t tri_staged;          /* sum over those tasks of the anchor forward-list length */
+    /* groups of consecutive hub tasks that one workgroup stages into a single LDS tile */
+    uint64_t hub_groups;          /* over the hub dyads */
+    uint64_t tri_groups;          /* over the hub edges of the forward lists */
 } tc_graph_info;
 
 /* Degree-bucket thresholds and launch sizes.  A dyad one of whose endpoints

@@ -70,6 +70,10 @@ graph_desc describe(const device_graph& g) {
     d.edges = g.tri.edges.recs;
     d.fwd = g.tri.fwd;
     d.edge_tasks = g.tri.edges.tasks;
+    d.hub_ntasks = g.n_hub_tasks;
+    d.hub_groups = g.n_hub_groups;
+    d.tri_tasks = g.tri.edges.n_tasks;
+    d.tri_groups = g.tri.edges.n_groups;
     return d;
 }
 
@@ -79,16 +83,16 @@ graph_desc describe(const device_graph& g) {
 void append_items(const device_graph& g, uint32_t gi, bool tri, std::vector<work_item>& hub,
                   std::vector<work_item>& out) {
     const uint64_t* off = g.bucket_off;
-    uint32_t ntasks = g.n_hub_tasks, flag = 0;
+    uint32_t ngroups = g.n_hub_groups, flag = 0;
     if (tri) {
         for (uint64_t e = 0; e < g.U; e += kBatchTotalsPerItem)
             out.push_back(work_item{gi, kItemTotals, (uint32_t)e,
                                     (uint32_t)std::min<uint64_t>(e + kBatchTotalsPerItem, g.U)});
         off = g.tri.edges.off;
-        ntasks = g.tri.edges.n_tasks;
+        ngroups = g.tri.edges.n_groups;
         flag = kItemTri;
     }
-    for (uint32_t t = 0; t < ntasks; ++t) hub.push_back(work_item{gi, kItemHub | flag, t, t + 1});
+    for (uint32_t t = 0; t < ngroups; ++t) hub.push_back(work_item{gi, kItemHub | flag, t, t + 1});
     for (uint64_t d = off[2]; d < off[3]; ++d)
         out.push_back(work_item{gi, kItemGroup | flag, (uint32_t)d, (uint32_t)d + 1});
     for (uint64_t d = off[1]; d < off[2]; d += kBatchWavePerItem)

@@ -483,8 +483,44 @@ __global__ __launch_bounds__(kT) void k_hub_emit(const unsigned int* __restrict_
         t.begin = (uint32_t)(base + j * kHubChunk);
         t.end = (uint32_t)(base + (c < (j + 1) * kHubChunk ? c : (j + 1) * kHubChunk));
         t.anchor = (uint32_t)h;
-        t.pad = 0;
+        t.group = 0;
         tasks[t0 + j] = t;
+    }
+}
+
+// Groups of consecutive hub tasks that one workgroup runs with a single LDS
+// tile: each window of kHubGroupTasks tasks is cut greedily before a task whose
+// records would take the group past kHubChunk or whose anchor row would take
+// the group's rows past kHubTileEntries (a row longer than that stays alone).
+// Without goff, counts the groups of every window into gcount; with goff (the
+// scanned counts), stores the first task of each group in tasks[g].group.
+__global__ __launch_bounds__(kT) void k_hub_group(hub_task* __restrict__ tasks, const dyad_rec* __restrict__ recs,
+                                                  uint64_t ntasks, const uint64_t* __restrict__ goff,
+                                                  uint64_t* __restrict__ gcount) {
+    const uint64_t w = (uint64_t)blockIdx.x * kT + threadIdx.x;
+    const uint64_t t0 = w * kHubGroupTasks;
+    if (t0 >= ntasks) return;
+    const uint32_t nt = (uint32_t)(ntasks - t0 < kHubGroupTasks ? ntasks - t0 : kHubGroupTasks);
+    uint32_t starts[kHubGroupTasks];
+    uint32_t ng = 0, gs = 0, sr = 0, se = 0;
+    for (uint32_t j = 0; j < nt; ++j) {
+        const uint32_t b = tasks[t0 + j].begin, e = tasks[t0 + j].end, a = tasks[t0 + j].anchor;
+        const dyad_rec r0 = recs[b];
+        const uint32_t l = r0.u == a ? r0.eu - r0.bu : r0.ev - r0.bv, r = e - b;
+        if (j > gs && (l > kHubTileEntries || sr + r > kHubChunk || se + l > kHubTileEntries)) {
+            starts[ng++] = gs;
+            gs = j;
+            sr = 0;
+            se = 0;
+        }
+        sr += r;
+        se += l;
+    }
+    starts[ng++] = gs;
+    if (goff == nullptr) {
+        gcount[w] = ng;
+    } else {
+        for (uint32_t k = 0; k < ng; ++k) tasks[goff[w] + k].group = (uint32_t)t0 + starts[k];
     }
 }
 
@@ -722,6 +758,25 @@ static hipError_t bucket_records(const uint32_t* nbr, const uint32_t* owner, con
             TRY(hipGetLastError());
         }
         out->n_tasks = (uint32_t)ntasks;
+        // groups of consecutive tasks
+        const uint64_t windows = (ntasks + kHubGroupTasks - 1) / kHubGroupTasks;
+        uint64_t* gcount = nullptr;
+        uint64_t ngroups = 0;
+        TRY(hipMallocAsync((void**)&gcount, sizeof(uint64_t) * (windows + 1), s));
+        hipLaunchKernelGGL(k_hub_group, dim3(grid1(windows)), dim3(kT), 0, s, out->tasks,
+                           (const dyad_rec*)out->recs, ntasks, (const uint64_t*)nullptr, gcount);
+        err = hipGetLastError();
+        if (err == hipSuccess) err = scan_exclusive_u64(gcount, gcount, windows, gcount + windows, s);
+        if (err == hipSuccess) {
+            hipLaunchKernelGGL(k_hub_group, dim3(grid1(windows)), dim3(kT), 0, s, out->tasks,
+                               (const dyad_rec*)out->recs, ntasks, (const uint64_t*)gcount, (uint64_t*)nullptr);
+            err = hipGetLastError();
+        }
+        if (err == hipSuccess) err = hipMemcpyAsync(&ngroups, gcount + windows, sizeof(uint64_t), hipMemcpyDeviceToHost, s);
+        if (err == hipSuccess) err = hipStreamSynchronize(s);
+        (void)hipFreeAsync(gcount, s);
+        if (err != hipSuccess) goto done;
+        out->n_groups = (uint32_t)ngroups;
     }
     TRY(hipMemcpyAsync(hc, counters, sizeof(hc), hipMemcpyDeviceToHost, s));
     TRY(hipStreamSynchronize(s));
@@ -789,12 +844,14 @@ hipError_t bucket_dyads(device_graph* g, const bucket_params& bp, hipStream_t s)
     g->dyads = nullptr;
     g->hub_tasks = nullptr;
     g->n_hub_tasks = 0;
+    g->n_hub_groups = 0;
     uint64_t mutual = 0;
     hipError_t err = bucket_records(g->nbr, g->owner, g->row_ptr, g->U, g->n, 0, bp, s, &d, &mutual);
     g->dyads = d.recs;
     g->hub_tasks = d.tasks;
     if (err != hipSuccess) return err;
     g->n_hub_tasks = d.n_tasks;
+    g->n_hub_groups = d.n_groups;
     g->p = d.off[kBuckets];
     for (int b = 0; b <= kBuckets; ++b) g->bucket_off[b] = d.off[b];
     for (int b = 0; b < kBuckets; ++b) g->bucket_cost[b] = d.cost[b];

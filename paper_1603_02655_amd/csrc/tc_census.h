@@ -32,7 +32,8 @@ struct graph_desc {
     const dyad_rec* edges;       // forward-list edge records (null without forward lists)
     const uint32_t* fwd;
     const hub_task* edge_tasks;
-    uint64_t pad;
+    uint32_t hub_ntasks, hub_groups;   // tasks and task groups over the dyad records
+    uint32_t tri_tasks, tri_groups;    // tasks and task groups over the edge records
 };
 // Item kinds: the mode (lane / wave / group / hub), with kItemTri when the item
 // indexes the forward-list edge records; kItemTotals covers neighbour entries
@@ -40,7 +41,7 @@ struct graph_desc {
 enum : uint32_t { kItemLane = 0, kItemWave = 1, kItemGroup = 2, kItemHub = 3, kItemTri = 4, kItemTotals = 8 };
 struct work_item {
     uint32_t graph, kind, begin, end;   // records [begin, end) of graph `graph`'s record array;
-                                        // hub items: hub tasks [begin, end) of the graph
+                                        // hub items: task groups [begin, end) of the graph
 };
 constexpr uint32_t kBatchTotalsPerItem = 4096;   // neighbour entries per totals item
 constexpr uint32_t kBatchLanePerItem = 256;   // one dyad per thread of a 256-thread workgroup

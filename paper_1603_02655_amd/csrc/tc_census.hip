@@ -74,6 +74,22 @@ struct lane_bins {
     }
 };
 
+// block_bins: one row shared by the workgroup (LDS atomics; used where updates
+// are rare next to the work that produces them).
+template <int B>
+struct block_bins {
+    static constexpr int kWords = kBins;
+    unsigned long long* bins;
+    __device__ inline void add(uint32_t cls, unsigned long long x) { atomicAdd(&bins[cls], x); }
+    __device__ inline void clear() {
+        for (int i = threadIdx.x; i < kWords; i += B) bins[i] = 0;
+    }
+    __device__ inline void flush(unsigned long long* acc) {
+        __syncthreads();
+        if (threadIdx.x < kNumClasses && bins[threadIdx.x] != 0) atomicAdd(&acc[threadIdx.x], bins[threadIdx.x]);
+    }
+};
+
 template <int B>
 struct wave_bins {
     static constexpr int kWords = kBins * (B / 64);
@@ -569,14 +585,15 @@ __global__ __launch_bounds__(kGroupB) void k_census_group(census_args L, unsigne
 
 
 // ----------------------------------------------------------------- hub ----
-// Hub records, grouped by anchor (their endpoint with the longer row).  A
-// workgroup takes one hub task (up to kHubChunk records that share the
-// anchor), stages the anchor's row tile by tile into an LDS hash table
-// (kHubTile entries in 4-slot buckets, the next bucket on overflow), and
-// streams the other endpoint's row of every record of the task against it:
-// each entry of that row is probed once, in the tile whose vertex range holds
-// it.  The anchor row is thus read once per task instead of once per record,
-// and the work per record is proportional to the shorter row.
+// Hub records, grouped by anchor (their endpoint with the longer row) into
+// hub tasks of up to kHubChunk records that share the anchor.  A workgroup
+// takes kHubGroupTasks consecutive tasks at a time, stages the anchor rows into
+// an LDS hash table (kHubTile entries in 4-slot buckets, the next bucket on
+// overflow) -- the rows of several tasks together when they fit one tile, a
+// longer row tile by tile -- and streams the other endpoint's row of every
+// record against it: each entry of that row is probed once, in the tile whose
+// vertex range holds it.  The anchor row is thus read once per task instead of
+// once per record, and the work per record is proportional to the shorter row.
 constexpr int kHubB = 256;
 constexpr uint32_t kHubTile = kHubTileEntries;
 constexpr uint32_t kHubBuckets = kHubTile / 2;           // buckets of 4 slots, mean load 2 entries
@@ -632,7 +649,9 @@ __device__ inline uint32_t hub_probe(const uint32_t* hash, uint32_t w) {
 }
 
 // Exclusive scan of a[0..count) in place on a 256-thread block (count <=
-// 4 * 256); a[count] receives the total.  wsum holds 4 words of LDS.
+// 4 * 256); a[count .. count + kScanPad) receive the total.  wsum holds 4 words
+// of LDS.
+constexpr uint32_t kScanPad = 8;
 __device__ inline void block_scan_u32(uint32_t* a, uint32_t count, uint32_t* wsum) {
     constexpr uint32_t kPer = kHubChunk / kHubB;
     const uint32_t tid = threadIdx.x, lane = tid & 63u, wid = tid >> 6;
@@ -661,7 +680,7 @@ __device__ inline void block_scan_u32(uint32_t* a, uint32_t count, uint32_t* wsu
         const uint32_t i = tid * kPer + k;
         if (i < count) a[i] = base + loc[k];
     }
-    if (tid == 0) a[count] = tot;
+    if (tid < kScanPad) a[count + tid] = tot;
     __syncthreads();
 }
 
@@ -694,14 +713,21 @@ struct hub_lds {
     uint2* ring;      // kHubRing x (kHubB / 64) candidates: (entry, meta word of its record)
     uint32_t* pos;    // next unprobed position in the other endpoint's row
     uint32_t* meta;   // (x << 3) | (anchor is u) << 2 | f_uv
-    uint32_t* off;    // probes of this tile, then their exclusive scan (kHubChunk + 1)
+    uint32_t* off;    // probes of this tile, then their exclusive scan and kScanPad copies of the total
     uint32_t* wsum;   // 4 words
     uint32_t* sig;    // kSigs counts shared by the workgroup
     uint32_t* filt;   // kHubFilterBits bits: a vertex whose bit is clear is not in the tile
+    uint32_t* tk;     // kHubTkWords: the tasks of the current chunk and their groups
 };
 constexpr uint32_t kHubFilterBits = 1u << (32 - kHubFilterShift);
-constexpr uint32_t kHubLdsWords = kHubSlots + 2 * kHubRing * (kHubB / 64) + 2 * kHubChunk + (kHubChunk + 4) + 4 +
-                                  kSigs + kHubFilterBits / 32;
+// Words of hub_lds::tk: per task of the chunk its first record, record count,
+// anchor-row start, anchor-row length and anchor; the group boundaries and
+// their count; the record and row prefixes of the current group's members.
+constexpr uint32_t kTkBegin = 0, kTkNrec = 8, kTkHb = 16, kTkLen = 24, kTkAnchor = 32, kTkGroups = 40,
+                   kTkNGroups = 49, kTkRb = 50, kTkEb = 59, kHubTkWords = 68;
+static_assert(kHubGroupTasks == 8, "the task words hold eight tasks");
+constexpr uint32_t kHubLdsWords = kHubSlots + 2 * kHubRing * (kHubB / 64) + 2 * kHubChunk + (kHubChunk + kScanPad) + 4 +
+                                  kSigs + kHubFilterBits / 32 + kHubTkWords;
 
 __device__ inline hub_lds hub_carve(uint32_t* base) {
     uint32_t* p = base;
@@ -710,10 +736,11 @@ __device__ inline hub_lds hub_carve(uint32_t* base) {
     S.ring = reinterpret_cast<uint2*>(p);  p += 2 * kHubRing * (kHubB / 64);
     S.pos = p;   p += kHubChunk;
     S.meta = p;  p += kHubChunk;
-    S.off = p;   p += kHubChunk + 4;
+    S.off = p;   p += kHubChunk + kScanPad;
     S.wsum = p;  p += 4;
     S.sig = p;   p += kSigs;
-    S.filt = p;
+    S.filt = p;  p += kHubFilterBits / 32;
+    S.tk = p;
     return S;
 }
 
@@ -738,51 +765,62 @@ __device__ inline void hub_bins_flush(const hub_lds& S, const uint8_t* T, H& h) 
     __syncthreads();
 }
 
-// One hub task on the whole workgroup (kHubB threads).  Per tile of the
-// anchor row: clear and fill the hash table; count, for every dyad, the
-// entries of the other row that fall in the tile's vertex range; scan the
-// counts; then each wavefront probes a quarter of the flattened (dyad, entry)
-// list, 64 adjacent entries per gather and kHubGather gathers in flight, and
-// probes the entries that pass the tile's filter 64 at a time.  A hit adds one
-// to the workgroup's count of the hit's signature.
+// One group of hub tasks on the whole workgroup (kHubB threads): members
+// [js, js + M) of the chunk's tasks, whose anchor rows together fit one tile
+// unless the group is a single task.  Per tile of the members' concatenated
+// anchor rows: clear and fill the hash table (an entry of member m is stored
+// with m above its 25 bits, so each record matches its own anchor only);
+// count, for every record, the entries of the other row that fall in the
+// tile's vertex range; scan the counts; then each wavefront probes a quarter of
+// the flattened (record, entry) list, 64 adjacent entries per gather and
+// kHubGather gathers in flight, and probes the entries that pass the tile's
+// filter 64 at a time.  A hit adds one to the workgroup's count of the hit's
+// signature.
 template <bool Tri, class H>
-__device__ inline void hub_task_run(const hub_task& tk, const dyad_rec* __restrict__ dyads,
-                                    const uint32_t* __restrict__ nbr, const uint64_t* __restrict__ tpre, uint64_t n,
-                                    uint32_t u_lo, uint32_t u_hi, const hub_lds& S, const uint8_t* T, H& h,
-                                    uint32_t& since) {
+__device__ inline void hub_group_run(uint32_t js, uint32_t M, const dyad_rec* __restrict__ dyads,
+                                     const uint32_t* __restrict__ nbr, const uint64_t* __restrict__ tpre, uint64_t n,
+                                     uint32_t u_lo, uint32_t u_hi, const hub_lds& S, const uint8_t* T, H& h,
+                                     uint32_t& since) {
     const uint32_t tid = threadIdx.x;
-    const uint32_t nrec = tk.end - tk.begin, a = tk.anchor;
-    const dyad_rec r0 = load_rec(dyads + tk.begin);
-    const uint32_t hb = r0.u == a ? r0.bu : r0.bv, he = r0.u == a ? r0.eu : r0.ev;
-    const bool multi_tile = he - hb > kHubTile;
+    const uint32_t* rb = S.tk + kTkRb;   // record prefix of the members (M + 1 words)
+    const uint32_t* eb = S.tk + kTkEb;   // anchor-row prefix of the members (M + 1 words)
+    const uint32_t nrec = rb[M], total = eb[M];
+    const bool multi_tile = total > kHubTile;   // a single task
     for (uint32_t i = tid; i < nrec; i += kHubB) {
-        const dyad_rec r = load_rec(dyads + tk.begin + i);
+        uint32_t m = 0;
+        while (m + 1 < M && rb[m + 1] <= i) ++m;
+        const uint32_t a = S.tk[kTkAnchor + js + m];
+        const dyad_rec r = load_rec(dyads + S.tk[kTkBegin + js + m] + (i - rb[m]));
         const bool anchor_u = r.u == a;
         const uint32_t x = anchor_u ? (r.vf >> 2) : r.u;
         const uint32_t xb = anchor_u ? r.bv : r.bu, xe = anchor_u ? r.ev : r.eu;
         const bool in = r.u >= u_lo && r.u < u_hi;
         S.pos[i] = in ? xb : xe;   // outside the requested range: nothing to probe
-        S.meta[i] = (x << 3) | (anchor_u ? 4u : 0u) | (r.vf & 3u);
+        S.meta[i] = (m << 26) | (x << 3) | (anchor_u ? 4u : 0u) | (r.vf & 3u);
         if (!multi_tile) S.off[i] = in ? xe - xb : 0u;
         if (!Tri && in) add_totals(r, load_totals(r, tpre), n, T, h);
     }
-    for (uint32_t tb = hb; tb < he; tb += kHubTile) {
-        const uint32_t te = min(he, tb + kHubTile);
+    for (uint32_t tb = 0; tb < total; tb += kHubTile) {
+        const uint32_t te = min(total, tb + kHubTile);
         for (uint32_t k = tid; k < kHubSlots; k += kHubB) S.hash[k] = kEmpty;
         for (uint32_t k = tid; k < kHubFilterBits / 32; k += kHubB) S.filt[k] = 0;
         __syncthreads();
-        for (uint32_t k = tb + tid; k < te; k += kHubB) {
-            hub_insert(S.hash, nbr[k]);
-            const uint32_t fb = hub_filter_bit(nbr[k] >> 2);
+        for (uint32_t f = tb + tid; f < te; f += kHubB) {
+            uint32_t m = 0;
+            while (m + 1 < M && eb[m + 1] <= f) ++m;
+            const uint32_t v = nbr[S.tk[kTkHb + js + m] + (f - eb[m])];
+            hub_insert(S.hash, (m << 25) | v);
+            const uint32_t fb = hub_filter_bit((m << 23) | (v >> 2));
             atomicOr(&S.filt[fb >> 5], 1u << (fb & 31u));
         }
         if (multi_tile) {
-            const uint32_t w_end = te < he ? (nbr[te] >> 2) : kEmpty;
+            const uint32_t hb = S.tk[kTkHb + js], a = S.tk[kTkAnchor + js];
+            const uint32_t w_end = te < total ? (nbr[hb + te] >> 2) : kEmpty;
             for (uint32_t i = tid; i < nrec; i += kHubB) {
                 const uint32_t p0 = S.pos[i];
                 uint32_t xe = p0;
                 if (p0 != 0xffffffffu) {
-                    const dyad_rec r = load_rec(dyads + tk.begin + i);
+                    const dyad_rec r = load_rec(dyads + S.tk[kTkBegin + js] + i);
                     xe = r.u == a ? r.ev : r.eu;
                 }
                 const uint32_t p1 = w_end == kEmpty ? xe : find_first_ge(nbr, p0, xe, w_end);
@@ -805,8 +843,8 @@ __device__ inline void hub_task_run(const hub_task& tk, const dyad_rec* __restri
         // walks it in windows of 64 * kHubGather entries; lane l takes entries
         // l, l + 64, ... of each window, so every gather reads 64 adjacent
         // entries (a few cache lines).  A lane keeps the record of its current
-        // entry and, prefetched, the start, position and meta word of the
-        // record after it: moving to the next record waits on no LDS read.
+        // entry and finds the record of the next one from the four record
+        // starts after it (by bisection beyond).
         // Entries that pass the filter are appended to the wavefront's ring of
         // candidates, and every 64 candidates are probed together, one per lane.
         const uint32_t lane = tid & 63u, wid = tid >> 6;
@@ -820,10 +858,11 @@ __device__ inline void hub_task_run(const hub_task& tk, const dyad_rec* __restri
             wave_sync{}();
             if (lane < c) {
                 const uint2 q = ring[(head + lane) & (kHubRing - 1)];
-                const uint32_t w = q.x >> 2;
-                const uint32_t hit = hub_probe(S.hash, w);
+                const uint32_t w = q.x >> 2, m = q.y >> 26;
+                const uint32_t hit = hub_probe(S.hash, (m << 23) | w);
                 if (hit != kEmpty) {
-                    const uint32_t x = q.y >> 3, fuv = q.y & 3u;
+                    const uint32_t a = S.tk[kTkAnchor + js + m];
+                    const uint32_t x = (q.y >> 3) & ((1u << 23) - 1u), fuv = q.y & 3u;
                     const bool anchor_u = (q.y & 4u) != 0;
                     const uint32_t u = anchor_u ? a : x, v = anchor_u ? x : a;
                     const uint32_t fx = q.x & 3u, fh = hit & 3u;
@@ -846,30 +885,6 @@ __device__ inline void hub_task_run(const hub_task& tk, const dyad_rec* __restri
                 }
             }
             uint32_t next = S.off[i + 1], base = S.pos[i] - S.off[i], m = S.meta[i];
-            uint32_t n_next = S.off[min(i + 2, nrec)], n_pos = S.pos[min(i + 1, nrec - 1)];
-            uint32_t n_m = S.meta[min(i + 1, nrec - 1)];
-            // record of ff >= off[i], any number of records ahead
-            auto seek = [&](uint32_t ff) {
-                // the next four record starts are read together; off[nrec] = P > ff bounds the look-ahead
-                const uint32_t o2 = S.off[min(i + 2, nrec)], o3 = S.off[min(i + 3, nrec)];
-                const uint32_t o4 = S.off[min(i + 4, nrec)], o5 = S.off[min(i + 5, nrec)];
-                i += 1u + (ff >= o2 ? 1u : 0u) + (ff >= o3 ? 1u : 0u) + (ff >= o4 ? 1u : 0u) + (ff >= o5 ? 1u : 0u);
-                next = S.off[i + 1];
-                if (ff >= next) {
-                    // further ahead: the last record starting at or before ff, by bisection
-                    uint32_t hi = nrec;
-                    while (hi - i > 1) {
-                        const uint32_t mid = (i + hi) >> 1;
-                        if (S.off[mid] <= ff) i = mid; else hi = mid;
-                    }
-                    next = S.off[i + 1];
-                }
-                base = S.pos[i] - S.off[i];
-                m = S.meta[i];
-                n_next = S.off[min(i + 2, nrec)];
-                n_pos = S.pos[min(i + 1, nrec - 1)];
-                n_m = S.meta[min(i + 1, nrec - 1)];
-            };
             for (uint32_t win = q0; win < q1; win += 64u * kHubGather) {
                 uint32_t e[kHubGather], mk[kHubGather];
 #pragma unroll
@@ -879,21 +894,23 @@ __device__ inline void hub_task_run(const hub_task& tk, const dyad_rec* __restri
                     mk[k] = m;
                     if (ff < q1) {
                         if (ff >= next) {
-                            // the record after i, from the prefetched words
-                            const uint32_t start = next;
-                            ++i;
-                            base = n_pos - start;
-                            m = n_m;
-                            next = n_next;
+                            // The record of ff from the next four record starts
+                            // (off[nrec ..] = P > ff past the last record), and by
+                            // bisection when it lies further ahead.
+                            const uint32_t o2 = S.off[i + 2], o3 = S.off[i + 3], o4 = S.off[i + 4], o5 = S.off[i + 5];
+                            i += 1u + (ff >= o2 ? 1u : 0u) + (ff >= o3 ? 1u : 0u) + (ff >= o4 ? 1u : 0u) +
+                                 (ff >= o5 ? 1u : 0u);
+                            next = S.off[i + 1];
                             if (ff >= next) {
-                                --i;                    // records without entries here: walk on from i
-                                next = start;
-                                seek(ff);
-                            } else {
-                                n_next = S.off[min(i + 2, nrec)];
-                                n_pos = S.pos[min(i + 1, nrec - 1)];
-                                n_m = S.meta[min(i + 1, nrec - 1)];
+                                uint32_t hi = nrec;
+                                while (hi - i > 1) {
+                                    const uint32_t mid = (i + hi) >> 1;
+                                    if (S.off[mid] <= ff) i = mid; else hi = mid;
+                                }
+                                next = S.off[i + 1];
                             }
+                            base = S.pos[i] - S.off[i];
+                            m = S.meta[i];
                         }
                         mk[k] = m;
                         e[k] = base + ff;       // position in the row array, gathered below
@@ -905,10 +922,11 @@ __device__ inline void hub_task_run(const hub_task& tk, const dyad_rec* __restri
                 // filter words of all the entries first, then the appends
                 uint32_t fw[kHubGather], pm = 0;
 #pragma unroll
-                for (uint32_t k = 0; k < kHubGather; ++k) fw[k] = S.filt[hub_filter_bit(e[k] >> 2) >> 5];
+                for (uint32_t k = 0; k < kHubGather; ++k)
+                    fw[k] = S.filt[hub_filter_bit(((mk[k] >> 26) << 23) | (e[k] >> 2)) >> 5];
 #pragma unroll
                 for (uint32_t k = 0; k < kHubGather; ++k) {
-                    const uint32_t fb = hub_filter_bit(e[k] >> 2);
+                    const uint32_t fb = hub_filter_bit(((mk[k] >> 26) << 23) | (e[k] >> 2));
                     pm |= (e[k] != kEmpty ? (fw[k] >> (fb & 31u)) & 1u : 0u) << k;
                 }
 #pragma unroll
@@ -936,15 +954,74 @@ __device__ inline void hub_task_run(const hub_task& tk, const dyad_rec* __restri
     }
 }
 
+// Hub tasks [t0, t1) (at most kHubGroupTasks) on the whole workgroup: their
+// descriptors and anchor rows are read once, and runs of consecutive tasks
+// whose records fit one chunk and whose anchor rows fit one tile are
+// processed together; a task whose anchor row spans several tiles runs alone.
+template <bool Tri, class H>
+__device__ inline void hub_chunk_run(const hub_task* __restrict__ tasks, uint32_t t0, uint32_t t1,
+                                     const dyad_rec* __restrict__ dyads, const uint32_t* __restrict__ nbr,
+                                     const uint64_t* __restrict__ tpre, uint64_t n, uint32_t u_lo, uint32_t u_hi,
+                                     const hub_lds& S, const uint8_t* T, H& h, uint32_t& since) {
+    const uint32_t tid = threadIdx.x, nt = t1 - t0;
+    if (tid < nt) {
+        const hub_task tk = tasks[t0 + tid];
+        const dyad_rec r0 = load_rec(dyads + tk.begin);
+        const bool au = r0.u == tk.anchor;
+        const uint32_t hb = au ? r0.bu : r0.bv, he = au ? r0.eu : r0.ev;
+        S.tk[kTkBegin + tid] = tk.begin;
+        S.tk[kTkNrec + tid] = tk.end - tk.begin;
+        S.tk[kTkHb + tid] = hb;
+        S.tk[kTkLen + tid] = he - hb;
+        S.tk[kTkAnchor + tid] = tk.anchor;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        uint32_t ng = 0, sr = 0, se = 0;
+        S.tk[kTkGroups] = 0;
+        for (uint32_t j = 0; j < nt; ++j) {
+            const uint32_t r = S.tk[kTkNrec + j], l = S.tk[kTkLen + j];
+            if (j > S.tk[kTkGroups + ng] && (l > kHubTile || sr + r > kHubChunk || se + l > kHubTile)) {
+                S.tk[kTkGroups + ++ng] = j;
+                sr = 0;
+                se = 0;
+            }
+            sr += r;
+            se += l;
+        }
+        S.tk[kTkGroups + ++ng] = nt;
+        S.tk[kTkNGroups] = ng;
+    }
+    __syncthreads();
+    const uint32_t ng = S.tk[kTkNGroups];
+    for (uint32_t g = 0; g < ng; ++g) {
+        const uint32_t js = S.tk[kTkGroups + g], M = S.tk[kTkGroups + g + 1] - js;
+        if (tid == 0) {
+            uint32_t r = 0, e = 0;
+            for (uint32_t m = 0; m < M; ++m) {
+                S.tk[kTkRb + m] = r;
+                S.tk[kTkEb + m] = e;
+                r += S.tk[kTkNrec + js + m];
+                e += S.tk[kTkLen + js + m];
+            }
+            S.tk[kTkRb + M] = r;
+            S.tk[kTkEb + M] = e;
+        }
+        __syncthreads();
+        hub_group_run<Tri>(js, M, dyads, nbr, tpre, n, u_lo, u_hi, S, T, h, since);
+        __syncthreads();
+    }
+}
+
 template <bool Tri>
 __global__ __launch_bounds__(kHubB) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_census_hub(census_args L, const hub_task* __restrict__ tasks,
-                                                      uint32_t ntasks, unsigned int* ctr) {
+                                                      uint32_t ntasks, uint32_t ngroups, unsigned int* ctr) {
     __shared__ __attribute__((aligned(16))) uint32_t hub_words[kHubLdsWords];
-    __shared__ unsigned long long bins[wave_bins<kHubB>::kWords];
+    __shared__ unsigned long long bins[block_bins<kHubB>::kWords];
     __shared__ uint8_t T[64];
     __shared__ uint32_t s_next;
     if (threadIdx.x < 64) T[threadIdx.x] = L.table[threadIdx.x];
-    wave_bins<kHubB> h{bins};
+    block_bins<kHubB> h{bins};
     h.clear();
     const hub_lds S = hub_carve(hub_words);
     hub_bins_clear(S);
@@ -953,13 +1030,13 @@ __global__ __launch_bounds__(kHubB) __attribute__((amdgpu_waves_per_eu(8, 8))) v
     const uint32_t xcd = blockIdx.x % kXcds;
     if (threadIdx.x == 0) s_next = take_chunk(ctr, xcd);
     __syncthreads();
-    uint32_t t = s_next;
+    uint32_t c = s_next;
     __syncthreads();
-    while (t < ntasks) {
+    while (c < ngroups) {
         if (threadIdx.x == 0) s_next = take_chunk(ctr, xcd);
-        hub_task_run<Tri>(tasks[t], L.dyads, L.nbr, L.tpre, L.n, L.u_lo, L.u_hi, S, T, h, since);
-        __syncthreads();
-        t = s_next;
+        const uint32_t t0 = tasks[c].group, t1 = c + 1 < ngroups ? tasks[c + 1].group : ntasks;
+        hub_chunk_run<Tri>(tasks, t0, t1, L.dyads, L.nbr, L.tpre, L.n, L.u_lo, L.u_hi, S, T, h, since);
+        c = s_next;
         __syncthreads();
     }
     hub_bins_flush<Tri>(S, T, h);
@@ -974,7 +1051,7 @@ __global__ __launch_bounds__(kHubB) __attribute__((amdgpu_waves_per_eu(8, 8))) v
 // of one graph's bucket, over its dyad records or its forward-list edge
 // records: up to 256 lane-mode records (one per thread), up to
 // 4 * kBatchWavePerItem wave-mode records (wavefront w takes every fourth), one
-// group-mode record, one hub task, or a chunk of the totals pass.  Counts go
+// group-mode record, one group of hub tasks, or a chunk of the totals pass.  Counts go
 // to per-wavefront bins that are flushed into the graph's 16 accumulators
 // whenever the workgroup moves to another graph.
 constexpr int kBatchB = 256;
@@ -1020,11 +1097,11 @@ __global__ __launch_bounds__(kHubB) __attribute__((amdgpu_waves_per_eu(8, 8))) v
     const graph_desc* __restrict__ G, const work_item* __restrict__ items, const uint32_t* __restrict__ nums,
     unsigned long long* __restrict__ accs, unsigned int* __restrict__ ctr) {
     __shared__ __attribute__((aligned(16))) uint32_t hub_words[kHubLdsWords];
-    __shared__ unsigned long long bins[wave_bins<kHubB>::kWords];
+    __shared__ unsigned long long bins[block_bins<kHubB>::kWords];
     __shared__ uint8_t T[64];
     __shared__ uint32_t s_next;
     if (threadIdx.x < 64) T[threadIdx.x] = c_table[threadIdx.x];
-    wave_bins<kHubB> h{bins};
+    block_bins<kHubB> h{bins};
     h.clear();
     const hub_lds S = hub_carve(hub_words);
     hub_bins_clear(S);
@@ -1055,11 +1132,15 @@ __global__ __launch_bounds__(kHubB) __attribute__((amdgpu_waves_per_eu(8, 8))) v
         }
         const graph_desc g = G[it.graph];
         for (uint32_t k = it.begin; k < it.end; ++k) {
-            if (cur_tri)
-                hub_task_run<true>(g.edge_tasks[k], g.edges, g.fwd, g.tpre, g.n, 0u, 0xffffffffu, S, T, h, since);
-            else
-                hub_task_run<false>(g.hub_tasks[k], g.dyads, g.nbr, g.tpre, g.n, 0u, 0xffffffffu, S, T, h, since);
-            __syncthreads();
+            if (cur_tri) {
+                const uint32_t t0 = g.edge_tasks[k].group;
+                const uint32_t t1 = k + 1 < g.tri_groups ? g.edge_tasks[k + 1].group : g.tri_tasks;
+                hub_chunk_run<true>(g.edge_tasks, t0, t1, g.edges, g.fwd, g.tpre, g.n, 0u, 0xffffffffu, S, T, h, since);
+            } else {
+                const uint32_t t0 = g.hub_tasks[k].group;
+                const uint32_t t1 = k + 1 < g.hub_groups ? g.hub_tasks[k + 1].group : g.hub_ntasks;
+                hub_chunk_run<false>(g.hub_tasks, t0, t1, g.dyads, g.nbr, g.tpre, g.n, 0u, 0xffffffffu, S, T, h, since);
+            }
         }
         idx = s_next;
         __syncthreads();
@@ -1184,10 +1265,11 @@ void launch_bucket(int b, const census_args& L, uint64_t cnt, const census_confi
 }
 
 template <bool Tri>
-void launch_hub(const census_args& L, const hub_task* tasks, uint32_t ntasks, const census_config& cfg,
-                unsigned int* counters, hipStream_t s) {
-    uint32_t grid = (uint32_t)std::min<uint64_t>(ntasks, cfg.hub_blocks);
-    hipLaunchKernelGGL(k_census_hub<Tri>, dim3(grid), dim3(kHubB), 0, s, L, tasks, ntasks, counters + 3 * kXcds);
+void launch_hub(const census_args& L, const hub_task* tasks, uint32_t ntasks, uint32_t ngroups,
+                const census_config& cfg, unsigned int* counters, hipStream_t s) {
+    uint32_t grid = (uint32_t)std::min<uint64_t>(ngroups, cfg.hub_blocks);
+    hipLaunchKernelGGL(k_census_hub<Tri>, dim3(grid), dim3(kHubB), 0, s, L, tasks, ntasks, ngroups,
+                       counters + 3 * kXcds);
 }
 
 }  // namespace
@@ -1201,6 +1283,7 @@ hipError_t census_launch(const device_graph& g, const census_slices& sl, bool tr
     const uint32_t* nbr = tri ? g.tri.fwd : g.nbr;
     const hub_task* tasks = tri ? g.tri.edges.tasks : g.hub_tasks;
     const uint32_t ntasks = tri ? g.tri.edges.n_tasks : g.n_hub_tasks;
+    const uint32_t ngroups = tri ? g.tri.edges.n_groups : g.n_hub_groups;
     if (tri) {
         if (ev) (void)hipEventRecord(ev[2 * kBuckets], s);
         if (g.U > 0) {
@@ -1220,8 +1303,8 @@ hipError_t census_launch(const device_graph& g, const census_slices& sl, bool tr
                           table};
             if (b == kBucketHub) {
                 L.dyads = recs;
-                if (tri) launch_hub<true>(L, tasks, ntasks, cfg, counters, s);
-                else launch_hub<false>(L, tasks, ntasks, cfg, counters, s);
+                if (tri) launch_hub<true>(L, tasks, ntasks, ngroups, cfg, counters, s);
+                else launch_hub<false>(L, tasks, ntasks, ngroups, cfg, counters, s);
             } else if (tri) {
                 launch_bucket<true>(b, L, cnt, cfg, counters, s);
             } else {

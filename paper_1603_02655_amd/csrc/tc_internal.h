@@ -12,7 +12,8 @@
 //                         partitioned into degree buckets; u-major inside the
 //                         merge buckets, anchor-major inside the hub bucket
 //   hub_tasks[]   hub_task runs of at most kHubChunk hub-bucket records that
-//                         share their anchor (the endpoint of larger degree)
+//                         share their anchor (the endpoint of larger degree),
+//                         and the first task of each group of tasks
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -36,11 +37,14 @@ struct __attribute__((aligned(16))) dyad_rec {
 static_assert(sizeof(dyad_rec) == 32, "dyad record is two 16-byte loads");
 
 // A run of hub-bucket records [begin, end) whose dyads all contain `anchor`.
+// Consecutive tasks form groups that a workgroup runs with one LDS tile;
+// `group` of task g holds the first task of group g (g below the group count).
 struct hub_task {
-    uint32_t begin, end, anchor, pad;
+    uint32_t begin, end, anchor, group;
 };
 constexpr uint32_t kHubChunk = 512;           // records per hub task
 constexpr uint32_t kHubTileEntries = 1024;    // anchor-row entries staged per LDS tile
+constexpr uint32_t kHubGroupTasks = 8;        // consecutive hub tasks a workgroup takes at a time
 
 // Bucket thresholds.  Dyads with max(|N(u)|, |N(v)|) >= t_hub go to the hub
 // bucket (anchored at the larger-degree endpoint, ties to the larger id); the

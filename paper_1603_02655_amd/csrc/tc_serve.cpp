@@ -107,7 +107,7 @@ uint64_t job_footprint(const job& j) {
         const device_graph& g = j.g->g;
         const bool tri = g.tri.fwd_ptr != nullptr;
         const uint64_t* off = tri ? g.tri.edges.off : g.bucket_off;
-        uint64_t items = (tri ? g.tri.edges.n_tasks : g.n_hub_tasks) + (off[3] - off[2]) +
+        uint64_t items = (tri ? g.tri.edges.n_groups : g.n_hub_groups) + (off[3] - off[2]) +
                          (off[2] - off[1] + kBatchWavePerItem - 1) / kBatchWavePerItem +
                          (off[1] - off[0] + kBatchLanePerItem - 1) / kBatchLanePerItem;
         if (tri) items += (g.U + kBatchTotalsPerItem - 1) / kBatchTotalsPerItem;

@@ -633,7 +633,7 @@ build_status build_graph_device(int32_t n, int64_t m, const int32_t* src_dev, co
     g->U = U;
     TRY(hipMallocAsync((void**)&degs, sizeof(uint64_t) * ((size_t)n + 1), s));
     TRY(fill_u64(degs, (uint64_t)n + 1, 0, s));
-    TRY(hipMalloc((void**)&g->nbr, sizeof(uint32_t) * (U ? U : 1)));
+    TRY(hipMalloc((void**)&g->nbr, sizeof(uint32_t) * (U + kRowPad)));
     TRY(hipMalloc((void**)&g->owner, sizeof(uint32_t) * (U ? U : 1)));
     TRY(hipMalloc((void**)&g->tpre, sizeof(uint64_t) * (U + 1)));
     if (valid > 0) {
@@ -821,7 +821,7 @@ static hipError_t build_forward(device_graph* g, hipStream_t s) {
     TRY(scan_exclusive_u64(pos, pos, U, pos + U, s));
     TRY(hipMemcpyAsync(&t.entries, pos + U, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
     TRY(hipStreamSynchronize(s));
-    TRY(hipMalloc((void**)&t.fwd, sizeof(uint32_t) * (t.entries ? t.entries : 1)));
+    TRY(hipMalloc((void**)&t.fwd, sizeof(uint32_t) * (t.entries + kRowPad)));
     TRY(hipMalloc((void**)&t.fwd_owner, sizeof(uint32_t) * (t.entries ? t.entries : 1)));
     if (U > 0) {
         hipLaunchKernelGGL(k_fwd_emit, dim3(grid1(U)), dim3(kT), 0, s, g->nbr, g->owner, U, (const uint64_t*)pos,
@@ -893,9 +893,10 @@ void free_device_graph(device_graph* g) {
 
 uint64_t device_graph_bytes(const device_graph& g) {
     uint64_t b = sizeof(int64_t) * ((uint64_t)g.n + 1) + (sizeof(uint32_t) * 2 + sizeof(uint64_t)) * g.U +
+                 sizeof(uint32_t) * kRowPad +
                  sizeof(uint64_t) + sizeof(dyad_rec) * g.p + sizeof(hub_task) * (uint64_t)g.n_hub_tasks;
     if (g.tri.fwd_ptr)
-        b += sizeof(int64_t) * ((uint64_t)g.n + 1) + sizeof(uint32_t) * 2 * g.tri.entries +
+        b += sizeof(int64_t) * ((uint64_t)g.n + 1) + sizeof(uint32_t) * (2 * g.tri.entries + kRowPad) +
              sizeof(dyad_rec) * g.tri.edges.off[kBuckets] + sizeof(hub_task) * (uint64_t)g.tri.edges.n_tasks;
     return b;
 }

@@ -705,15 +705,24 @@ struct scaled_bins {
     __device__ inline void add(uint32_t cls, unsigned long long x) { h.add(cls, x * c); }
 };
 
-// LDS of the hub mode: the hash table, one candidate ring per wavefront, three
-// per-dyad arrays, scan scratch, the signature histogram and the filter.
+// Aligned blocks of kHubGather entries that hold the entries [p0, p1) of a row
+// (row arrays are padded so that the last block is readable).
+static_assert(kHubGather == 8, "a block is read as two 16-byte loads");
+__device__ inline uint32_t hub_blocks(uint32_t p0, uint32_t p1) {
+    return p1 > p0 ? (p1 + kHubGather - 1) / kHubGather - p0 / kHubGather : 0u;
+}
+
+// LDS of the hub mode: the hash table, one candidate ring per wavefront, four
+// per-record arrays, scan scratch, the signature histogram, the filter and the
+// task words.
 constexpr uint32_t kHubRing = 128;   // candidates a wavefront holds between probe rounds
 struct hub_lds {
     uint32_t* hash;   // kHubSlots, 16-byte aligned
     uint2* ring;      // kHubRing x (kHubB / 64) candidates: (entry, meta word of its record)
     uint32_t* pos;    // next unprobed position in the other endpoint's row
+    uint32_t* end;    // end of that row's entries in the current tile
     uint32_t* meta;   // (x << 3) | (anchor is u) << 2 | f_uv
-    uint32_t* off;    // probes of this tile, then their exclusive scan and kScanPad copies of the total
+    uint32_t* off;    // blocks of this tile, then their exclusive scan and kScanPad copies of the total
     uint32_t* wsum;   // 4 words
     uint32_t* sig;    // kSigs counts shared by the workgroup
     uint32_t* filt;   // kHubFilterBits bits: a vertex whose bit is clear is not in the tile
@@ -726,7 +735,7 @@ constexpr uint32_t kHubFilterBits = 1u << (32 - kHubFilterShift);
 constexpr uint32_t kTkBegin = 0, kTkNrec = 8, kTkHb = 16, kTkLen = 24, kTkAnchor = 32, kTkGroups = 40,
                    kTkNGroups = 49, kTkRb = 50, kTkEb = 59, kHubTkWords = 68;
 static_assert(kHubGroupTasks == 8, "the task words hold eight tasks");
-constexpr uint32_t kHubLdsWords = kHubSlots + 2 * kHubRing * (kHubB / 64) + 2 * kHubChunk + (kHubChunk + kScanPad) + 4 +
+constexpr uint32_t kHubLdsWords = kHubSlots + 2 * kHubRing * (kHubB / 64) + 3 * kHubChunk + (kHubChunk + kScanPad) + 4 +
                                   kSigs + kHubFilterBits / 32 + kHubTkWords;
 
 __device__ inline hub_lds hub_carve(uint32_t* base) {
@@ -735,6 +744,7 @@ __device__ inline hub_lds hub_carve(uint32_t* base) {
     S.hash = p;  p += kHubSlots;
     S.ring = reinterpret_cast<uint2*>(p);  p += 2 * kHubRing * (kHubB / 64);
     S.pos = p;   p += kHubChunk;
+    S.end = p;   p += kHubChunk;
     S.meta = p;  p += kHubChunk;
     S.off = p;   p += kHubChunk + kScanPad;
     S.wsum = p;  p += 4;
@@ -795,9 +805,13 @@ __device__ inline void hub_group_run(uint32_t js, uint32_t M, const dyad_rec* __
         const uint32_t x = anchor_u ? (r.vf >> 2) : r.u;
         const uint32_t xb = anchor_u ? r.bv : r.bu, xe = anchor_u ? r.ev : r.eu;
         const bool in = r.u >= u_lo && r.u < u_hi;
-        S.pos[i] = in ? xb : xe;   // outside the requested range: nothing to probe
+        const uint32_t p0 = in ? xb : xe;   // outside the requested range: nothing to probe
+        S.pos[i] = p0;
         S.meta[i] = (m << 26) | (x << 3) | (anchor_u ? 4u : 0u) | (r.vf & 3u);
-        if (!multi_tile) S.off[i] = in ? xe - xb : 0u;
+        if (!multi_tile) {
+            S.end[i] = xe;
+            S.off[i] = hub_blocks(p0, xe);
+        }
         if (!Tri && in) add_totals(r, load_totals(r, tpre), n, T, h);
     }
     for (uint32_t tb = 0; tb < total; tb += kHubTile) {
@@ -824,29 +838,30 @@ __device__ inline void hub_group_run(uint32_t js, uint32_t M, const dyad_rec* __
                     xe = r.u == a ? r.ev : r.eu;
                 }
                 const uint32_t p1 = w_end == kEmpty ? xe : find_first_ge(nbr, p0, xe, w_end);
-                S.off[i] = p1 - p0;
+                S.end[i] = p1;
+                S.off[i] = hub_blocks(p0, p1);
             }
         }
         __syncthreads();
         block_scan_u32(S.off, nrec, S.wsum);
         const uint32_t P = S.off[nrec];
-        // The shared 32-bit signature counts grow by at most P in this tile:
-        // they are flushed first when the tiles since the last flush could
-        // take them past 2^32 (`per` is the same on every thread).
-        const uint32_t per = (P + kHubB - 1) / kHubB;
+        // The shared 32-bit signature counts grow by at most kHubGather * P in
+        // this tile: they are flushed first when the tiles since the last flush
+        // could take them past 2^32 (`per` is the same on every thread).
+        const uint32_t per = (uint32_t)min((uint64_t)kHubGather * P / kHubB + 1, (uint64_t)kHubFlushAfter);
         if (since + per > kHubFlushAfter) {
             hub_bins_flush<Tri>(S, T, h);
             since = 0;
         }
         since += per;
-        // Wavefront w takes the w-th quarter [q0, q1) of the flattened list and
-        // walks it in windows of 64 * kHubGather entries; lane l takes entries
-        // l, l + 64, ... of each window, so every gather reads 64 adjacent
-        // entries (a few cache lines).  A lane keeps the record of its current
-        // entry and finds the record of the next one from the four record
-        // starts after it (by bisection beyond).
-        // Entries that pass the filter are appended to the wavefront's ring of
-        // candidates, and every 64 candidates are probed together, one per lane.
+        // The rows to probe are cut into aligned blocks of kHubGather entries
+        // (a row's first and last block masked to the row).  Wavefront w takes
+        // the w-th quarter [q0, q1) of the flattened list of blocks and walks it
+        // 64 blocks at a time, one block per lane, read with two 16-byte loads.
+        // A lane finds the record of its next block from the four record
+        // starts after its current one (by bisection beyond).  Entries that
+        // pass the filter are appended to the wavefront's ring of candidates,
+        // and every 64 candidates are probed together, one per lane.
         const uint32_t lane = tid & 63u, wid = tid >> 6;
         constexpr uint32_t kWaves = kHubB / 64;
         const uint32_t q0 = (uint32_t)(((uint64_t)P * wid) / kWaves), q1 = (uint32_t)(((uint64_t)P * (wid + 1)) / kWaves);
@@ -884,49 +899,50 @@ __device__ inline void hub_group_run(uint32_t js, uint32_t M, const dyad_rec* __
                     if (S.off[mid] <= first) i = mid; else hi = mid;
                 }
             }
-            uint32_t next = S.off[i + 1], base = S.pos[i] - S.off[i], m = S.meta[i];
-            for (uint32_t win = q0; win < q1; win += 64u * kHubGather) {
-                uint32_t e[kHubGather], mk[kHubGather];
+            uint32_t next = S.off[i + 1], p0 = S.pos[i], p1 = S.end[i], m = S.meta[i];
+            uint32_t bb = p0 / kHubGather - S.off[i];   // block of flattened index f: bb + f (mod 2^32)
+            for (uint32_t win = q0; win < q1; win += 64u) {
+                const uint32_t f = win + lane;
+                uint32_t e[kHubGather];
 #pragma unroll
-                for (uint32_t k = 0; k < kHubGather; ++k) {
-                    const uint32_t ff = win + 64u * k + lane;
-                    e[k] = kEmpty;
-                    mk[k] = m;
-                    if (ff < q1) {
-                        if (ff >= next) {
-                            // The record of ff from the next four record starts
-                            // (off[nrec ..] = P > ff past the last record), and by
-                            // bisection when it lies further ahead.
-                            const uint32_t o2 = S.off[i + 2], o3 = S.off[i + 3], o4 = S.off[i + 4], o5 = S.off[i + 5];
-                            i += 1u + (ff >= o2 ? 1u : 0u) + (ff >= o3 ? 1u : 0u) + (ff >= o4 ? 1u : 0u) +
-                                 (ff >= o5 ? 1u : 0u);
-                            next = S.off[i + 1];
-                            if (ff >= next) {
-                                uint32_t hi = nrec;
-                                while (hi - i > 1) {
-                                    const uint32_t mid = (i + hi) >> 1;
-                                    if (S.off[mid] <= ff) i = mid; else hi = mid;
-                                }
-                                next = S.off[i + 1];
+                for (uint32_t k = 0; k < kHubGather; ++k) e[k] = kEmpty;
+                if (f < q1) {
+                    if (f >= next) {
+                        // The record of f from the next four record starts
+                        // (off[nrec ..] = P > f past the last record), and by
+                        // bisection when it lies further ahead.
+                        const uint32_t o2 = S.off[i + 2], o3 = S.off[i + 3], o4 = S.off[i + 4], o5 = S.off[i + 5];
+                        i += 1u + (f >= o2 ? 1u : 0u) + (f >= o3 ? 1u : 0u) + (f >= o4 ? 1u : 0u) + (f >= o5 ? 1u : 0u);
+                        next = S.off[i + 1];
+                        if (f >= next) {
+                            uint32_t hi = nrec;
+                            while (hi - i > 1) {
+                                const uint32_t mid = (i + hi) >> 1;
+                                if (S.off[mid] <= f) i = mid; else hi = mid;
                             }
-                            base = S.pos[i] - S.off[i];
-                            m = S.meta[i];
+                            next = S.off[i + 1];
                         }
-                        mk[k] = m;
-                        e[k] = base + ff;       // position in the row array, gathered below
+                        p0 = S.pos[i];
+                        p1 = S.end[i];
+                        m = S.meta[i];
+                        bb = p0 / kHubGather - S.off[i];
                     }
-                }
-                // every gather of the window in flight together
+                    const uint32_t b0 = (bb + f) * kHubGather;   // first entry of the block
+                    const uint4* src = reinterpret_cast<const uint4*>(nbr + b0);
+                    const uint4 lo = src[0], hi = src[1];
+                    const uint32_t v[kHubGather] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
 #pragma unroll
-                for (uint32_t k = 0; k < kHubGather; ++k) e[k] = e[k] != kEmpty ? nbr[e[k]] : kEmpty;
+                    for (uint32_t k = 0; k < kHubGather; ++k)
+                        e[k] = (b0 + k >= p0 && b0 + k < p1) ? v[k] : kEmpty;
+                }
                 // filter words of all the entries first, then the appends
                 uint32_t fw[kHubGather], pm = 0;
 #pragma unroll
                 for (uint32_t k = 0; k < kHubGather; ++k)
-                    fw[k] = S.filt[hub_filter_bit(((mk[k] >> 26) << 23) | (e[k] >> 2)) >> 5];
+                    fw[k] = S.filt[hub_filter_bit(((m >> 26) << 23) | (e[k] >> 2)) >> 5];
 #pragma unroll
                 for (uint32_t k = 0; k < kHubGather; ++k) {
-                    const uint32_t fb = hub_filter_bit(((mk[k] >> 26) << 23) | (e[k] >> 2));
+                    const uint32_t fb = hub_filter_bit(((m >> 26) << 23) | (e[k] >> 2));
                     pm |= (e[k] != kEmpty ? (fw[k] >> (fb & 31u)) & 1u : 0u) << k;
                 }
 #pragma unroll
@@ -936,7 +952,7 @@ __device__ inline void hub_group_run(uint32_t js, uint32_t M, const dyad_rec* __
                     if (pass) {
                         const uint32_t r = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
                                                                      __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
-                        ring[(head + cnt + r) & (kHubRing - 1)] = make_uint2(e[k], mk[k]);
+                        ring[(head + cnt + r) & (kHubRing - 1)] = make_uint2(e[k], m);
                     }
                     cnt += (uint32_t)__popcll(bal);
                     if (cnt >= 64u) {
@@ -949,7 +965,7 @@ __device__ inline void hub_group_run(uint32_t js, uint32_t M, const dyad_rec* __
         }
         __syncthreads();
         if (multi_tile)
-            for (uint32_t i = tid; i < nrec; i += kHubB) S.pos[i] += S.off[i + 1] - S.off[i];
+            for (uint32_t i = tid; i < nrec; i += kHubB) S.pos[i] = S.end[i];
         __syncthreads();
     }
 }
@@ -1014,7 +1030,7 @@ __device__ inline void hub_chunk_run(const hub_task* __restrict__ tasks, uint32_
 }
 
 template <bool Tri>
-__global__ __launch_bounds__(kHubB) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_census_hub(census_args L, const hub_task* __restrict__ tasks,
+__global__ __launch_bounds__(kHubB) __attribute__((amdgpu_waves_per_eu(7, 7))) void k_census_hub(census_args L, const hub_task* __restrict__ tasks,
                                                       uint32_t ntasks, uint32_t ngroups, unsigned int* ctr) {
     __shared__ __attribute__((aligned(16))) uint32_t hub_words[kHubLdsWords];
     __shared__ unsigned long long bins[block_bins<kHubB>::kWords];
@@ -1093,7 +1109,7 @@ __device__ inline void batch_item(uint32_t kind, const work_item& it, const grap
     }
 }
 
-__global__ __launch_bounds__(kHubB) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_census_batch_hub(
+__global__ __launch_bounds__(kHubB) __attribute__((amdgpu_waves_per_eu(7, 7))) void k_census_batch_hub(
     const graph_desc* __restrict__ G, const work_item* __restrict__ items, const uint32_t* __restrict__ nums,
     unsigned long long* __restrict__ accs, unsigned int* __restrict__ ctr) {
     __shared__ __attribute__((aligned(16))) uint32_t hub_words[kHubLdsWords];

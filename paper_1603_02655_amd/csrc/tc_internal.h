@@ -45,6 +45,7 @@ struct hub_task {
 constexpr uint32_t kHubChunk = 512;           // records per hub task
 constexpr uint32_t kHubTileEntries = 1024;    // anchor-row entries staged per LDS tile
 constexpr uint32_t kHubGroupTasks = 8;        // consecutive hub tasks a workgroup takes at a time
+constexpr uint64_t kRowPad = 8;               // entries allocated past the end of a row array (block reads)
 
 // Bucket thresholds.  Dyads with max(|N(u)|, |N(v)|) >= t_hub go to the hub
 // bucket (anchored at the larger-degree endpoint, ties to the larger id); the

@@ -617,7 +617,8 @@ __device__ inline uint32_t hub_bucket(uint32_t w) { return (w * 0x9E3779B1u) >> 
 
 // Bit of a vertex in the tile's filter (another multiplier than the buckets').
 constexpr uint32_t kHubFilterShift = 32 - 13;
-__device__ inline uint32_t hub_filter_bit(uint32_t w) { return (w * 0x85EBCA6Bu) >> kHubFilterShift; }
+constexpr uint32_t kHubFilterMul = 0x85EBCA6Bu;
+__device__ inline uint32_t hub_filter_bit(uint32_t w) { return (w * kHubFilterMul) >> kHubFilterShift; }
 
 // Buckets fill their slots in order, so a bucket whose last slot is empty
 // ends the probe sequence of every vertex that hashes to it or before it.
@@ -866,13 +867,13 @@ __device__ inline void hub_group_run(uint32_t js, uint32_t M, const dyad_rec* __
         constexpr uint32_t kWaves = kHubB / 64;
         const uint32_t q0 = (uint32_t)(((uint64_t)P * wid) / kWaves), q1 = (uint32_t)(((uint64_t)P * (wid + 1)) / kWaves);
         uint2* ring = S.ring + wid * kHubRing;
-        uint32_t head = 0, cnt = 0;   // the same on every lane: ring[head, head + cnt) waits to be probed
-        // Probes ring[head + l] on the lanes l < c (c <= 64): a hit adds one to
-        // the count of its signature.
+        uint32_t cnt = 0;   // the same on every lane: ring[0, cnt) waits to be probed
+        // Probes ring[l] on the lanes l < c (c <= 64): a hit adds one to the
+        // count of its signature.
         auto probe_round = [&](uint32_t c) {
             wave_sync{}();
             if (lane < c) {
-                const uint2 q = ring[(head + lane) & (kHubRing - 1)];
+                const uint2 q = ring[lane];
                 const uint32_t w = q.x >> 2, m = q.y >> 26;
                 const uint32_t hit = hub_probe(S.hash, (m << 23) | w);
                 if (hit != kEmpty) {
@@ -886,7 +887,6 @@ __device__ inline void hub_group_run(uint32_t js, uint32_t M, const dyad_rec* __
                 }
             }
             wave_sync{}();
-            head += c;
         };
         if (q0 < q1) {
             uint32_t i = 0;
@@ -903,9 +903,9 @@ __device__ inline void hub_group_run(uint32_t js, uint32_t M, const dyad_rec* __
             uint32_t bb = p0 / kHubGather - S.off[i];   // block of flattened index f: bb + f (mod 2^32)
             for (uint32_t win = q0; win < q1; win += 64u) {
                 const uint32_t f = win + lane;
-                uint32_t e[kHubGather];
+                uint32_t e[kHubGather], vm = 0;   // the block's words; bit k: word k is an entry of the row
 #pragma unroll
-                for (uint32_t k = 0; k < kHubGather; ++k) e[k] = kEmpty;
+                for (uint32_t k = 0; k < kHubGather; ++k) e[k] = 0;
                 if (f < q1) {
                     if (f >= next) {
                         // The record of f from the next four record starts
@@ -927,37 +927,45 @@ __device__ inline void hub_group_run(uint32_t js, uint32_t M, const dyad_rec* __
                         m = S.meta[i];
                         bb = p0 / kHubGather - S.off[i];
                     }
-                    const uint32_t b0 = (bb + f) * kHubGather;   // first entry of the block
+                    const uint32_t b0 = (bb + f) * kHubGather;   // first entry of the block: b0 < p1, p0 < b0 + 8
                     const uint4* src = reinterpret_cast<const uint4*>(nbr + b0);
-                    const uint4 lo = src[0], hi = src[1];
-                    const uint32_t v[kHubGather] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
-#pragma unroll
-                    for (uint32_t k = 0; k < kHubGather; ++k)
-                        e[k] = (b0 + k >= p0 && b0 + k < p1) ? v[k] : kEmpty;
+                    const uint4 lo4 = src[0], hi4 = src[1];
+                    e[0] = lo4.x; e[1] = lo4.y; e[2] = lo4.z; e[3] = lo4.w;
+                    e[4] = hi4.x; e[5] = hi4.y; e[6] = hi4.z; e[7] = hi4.w;
+                    const uint32_t klo = p0 > b0 ? p0 - b0 : 0u, khi = min(p1 - b0, kHubGather);
+                    vm = ((1u << khi) - 1u) & ~((1u << klo) - 1u);
                 }
-                // filter words of all the entries first, then the appends
-                uint32_t fw[kHubGather], pm = 0;
-#pragma unroll
-                for (uint32_t k = 0; k < kHubGather; ++k)
-                    fw[k] = S.filt[hub_filter_bit(((m >> 26) << 23) | (e[k] >> 2)) >> 5];
+                // Filter: the word of every entry first, then the bits.  The
+                // filter of a key k has bit (k * C) >> kHubFilterShift set.
+                const uint32_t mkey = (m >> 26) << 23;
+                uint32_t hk[kHubGather], fw[kHubGather], pm = 0;
 #pragma unroll
                 for (uint32_t k = 0; k < kHubGather; ++k) {
-                    const uint32_t fb = hub_filter_bit(((m >> 26) << 23) | (e[k] >> 2));
-                    pm |= (e[k] != kEmpty ? (fw[k] >> (fb & 31u)) & 1u : 0u) << k;
+                    hk[k] = (mkey | (e[k] >> 2)) * kHubFilterMul;
+                    fw[k] = S.filt[hk[k] >> (kHubFilterShift + 5)];
                 }
+#pragma unroll
+                for (uint32_t k = 0; k < kHubGather; ++k) pm |= ((fw[k] >> ((hk[k] >> kHubFilterShift) & 31u)) & 1u) << k;
+                pm &= vm;
+                // appends: the entries that pass go to ring[cnt ..] in lane order
 #pragma unroll
                 for (uint32_t k = 0; k < kHubGather; ++k) {
                     const bool pass = (pm >> k) & 1u;
                     const unsigned long long bal = __ballot(pass);
                     if (pass) {
                         const uint32_t r = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
-                                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
-                        ring[(head + cnt + r) & (kHubRing - 1)] = make_uint2(e[k], m);
+                                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)bal, cnt));
+                        ring[r] = make_uint2(e[k], m);
                     }
                     cnt += (uint32_t)__popcll(bal);
                     if (cnt >= 64u) {
                         probe_round(64u);
                         cnt -= 64u;
+                        // the rest moves to the front
+                        uint2 t = make_uint2(0u, 0u);
+                        if (lane < cnt) t = ring[64u + lane];
+                        wave_sync{}();
+                        if (lane < cnt) ring[lane] = t;
                     }
                 }
             }

@@ -62,6 +62,7 @@ graph_desc describe(const device_graph& g) {
     d.dyads = g.dyads;
     d.nbr = g.nbr;
     d.tpre = g.tpre;
+    d.rinfo = g.rinfo;
     d.n = (uint64_t)g.n;
     d.hub_tasks = g.hub_tasks;
     d.owner = g.owner;

@@ -44,6 +44,7 @@ struct device_graph {
     uint32_t* nbr = nullptr;
     uint32_t* owner = nullptr; // row of each entry (used to rebuild the buckets)
     uint64_t* tpre = nullptr;
+    uint4* rinfo = nullptr;    // per row x: row_ptr[x], row_ptr[x+1] and the prefix counts tpre[row_ptr[x+1]]
     dyad_rec* dyads = nullptr;
     hub_task* hub_tasks = nullptr;
     uint32_t n_hub_tasks = 0;

@@ -242,6 +242,16 @@ __global__ __launch_bounds__(kT) void k_type_bits(const uint32_t* __restrict__ n
     }
 }
 
+// Per row: its bounds and the direction-bit prefix counts at its end.
+__global__ __launch_bounds__(kT) void k_row_info(const int64_t* __restrict__ row_ptr, int32_t n,
+                                                 const uint64_t* __restrict__ tpre, uint4* __restrict__ rinfo) {
+    int32_t x = (int32_t)(blockIdx.x * kT + threadIdx.x);
+    if (x < n) {
+        const uint64_t rb = (uint64_t)row_ptr[x], re = (uint64_t)row_ptr[x + 1], t = tpre[re];
+        rinfo[x] = make_uint4((uint32_t)rb, (uint32_t)re, (uint32_t)t, (uint32_t)(t >> 32));
+    }
+}
+
 // degree statistics: max degree, sum of squares
 __global__ __launch_bounds__(kT) void k_deg_stats(const int64_t* __restrict__ row_ptr, int32_t n,
                                                    unsigned long long* __restrict__ counters) {
@@ -648,6 +658,12 @@ build_status build_graph_device(int32_t n, int64_t m, const int32_t* src_dev, co
         TRY(hipGetLastError());
     }
     TRY(scan_exclusive_u64(g->tpre, g->tpre, U, g->tpre + U, s));
+    TRY(hipMalloc((void**)&g->rinfo, sizeof(uint4) * ((size_t)n + 1)));
+    if (n > 0) {
+        hipLaunchKernelGGL(k_row_info, dim3(grid1((uint64_t)n)), dim3(kT), 0, s, (const int64_t*)g->row_ptr, n,
+                           (const uint64_t*)g->tpre, g->rinfo);
+        TRY(hipGetLastError());
+    }
     if (n > 0) {
         hipLaunchKernelGGL(k_deg_stats, dim3(grid1((uint64_t)n)), dim3(kT), 0, s, g->row_ptr, n, counters);
         TRY(hipGetLastError());
@@ -884,6 +900,7 @@ void free_device_graph(device_graph* g) {
     if (g->nbr) (void)hipFree(g->nbr);
     if (g->owner) (void)hipFree(g->owner);
     if (g->tpre) (void)hipFree(g->tpre);
+    if (g->rinfo) (void)hipFree(g->rinfo);
     if (g->dyads) (void)hipFree(g->dyads);
     if (g->hub_tasks) (void)hipFree(g->hub_tasks);
     int32_t n = g->n;
@@ -893,7 +910,7 @@ void free_device_graph(device_graph* g) {
 
 uint64_t device_graph_bytes(const device_graph& g) {
     uint64_t b = sizeof(int64_t) * ((uint64_t)g.n + 1) + (sizeof(uint32_t) * 2 + sizeof(uint64_t)) * g.U +
-                 sizeof(uint32_t) * kRowPad +
+                 sizeof(uint32_t) * kRowPad + sizeof(uint4) * ((uint64_t)g.n + 1) +
                  sizeof(uint64_t) + sizeof(dyad_rec) * g.p + sizeof(hub_task) * (uint64_t)g.n_hub_tasks;
     if (g.tri.fwd_ptr)
         b += sizeof(int64_t) * ((uint64_t)g.n + 1) + sizeof(uint32_t) * (2 * g.tri.entries + kRowPad) +

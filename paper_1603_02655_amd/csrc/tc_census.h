@@ -32,6 +32,7 @@ struct graph_desc {
     const dyad_rec* edges;       // forward-list edge records (null without forward lists)
     const uint32_t* fwd;
     const hub_task* edge_tasks;
+    const uint4* rinfo;          // per row: bounds and prefix counts at its end
     uint32_t hub_ntasks, hub_groups;   // tasks and task groups over the dyad records
     uint32_t tri_tasks, tri_groups;    // tasks and task groups over the edge records
 };

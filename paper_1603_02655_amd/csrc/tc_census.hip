@@ -283,14 +283,15 @@ __global__ __launch_bounds__(kLaneB) void k_census_lane(census_args L) {
 // entries after y in row x.  When y > x these are the entries of N(u) above v
 // for the dyad (u, v) = (x, y); when y < x they are the entries of N(v) above
 // u for the dyad (y, x).  The dyadic base n - |N(u)| - |N(v)| is split the
-// same way: n - |N(x)| from the first side, -|N(x)| from the second.  Every
-// read is coalesced (the row of an entry is shared by its neighbours).
+// same way: n - |N(x)| from the first side, -|N(x)| from the second.  The
+// entry arrays are read coalesced, and the row's bounds and prefix counts at
+// its end come in one 16-byte record shared by the row's entries.
 //
 // totals_entries: entries base + k * B + threadIdx.x (k < kPer) below `end`,
 // their loads issued before any is used.
 template <uint32_t kPer, uint32_t B, class H>
 __device__ inline void totals_entries(uint64_t base, uint64_t end, const uint32_t* __restrict__ nbr,
-                                      const uint32_t* __restrict__ owner, const int64_t* __restrict__ row_ptr,
+                                      const uint32_t* __restrict__ owner, const uint4* __restrict__ rinfo,
                                       const uint64_t* __restrict__ tpre, uint64_t n, const uint8_t* T, H& h) {
     uint32_t x[kPer], ent[kPer];
     uint64_t rb[kPer], re[kPer], pend[kPer], pnext[kPer];
@@ -303,11 +304,11 @@ __device__ inline void totals_entries(uint64_t base, uint64_t end, const uint32_
     }
 #pragma unroll
     for (uint32_t k = 0; k < kPer; ++k) {
-        rb[k] = (uint64_t)row_ptr[x[k]];
-        re[k] = (uint64_t)row_ptr[x[k] + 1];
+        const uint4 ri = rinfo[x[k]];
+        rb[k] = ri.x;
+        re[k] = ri.y;
+        pend[k] = (uint64_t)ri.z | ((uint64_t)ri.w << 32);
     }
-#pragma unroll
-    for (uint32_t k = 0; k < kPer; ++k) pend[k] = tpre[re[k]];
 #pragma unroll
     for (uint32_t k = 0; k < kPer; ++k) {
         const uint64_t e = base + k * B + threadIdx.x;
@@ -383,7 +384,7 @@ __device__ inline void slots_flush(unsigned long long* sbins, const uint32_t* bi
 
 __global__ __launch_bounds__(kLaneB) void k_census_totals(const uint32_t* __restrict__ nbr,
                                                           const uint32_t* __restrict__ owner,
-                                                          const int64_t* __restrict__ row_ptr,
+                                                          const uint4* __restrict__ rinfo,
                                                           const uint64_t* __restrict__ tpre, uint64_t U, uint64_t n,
                                                           const uint8_t* __restrict__ table,
                                                           unsigned long long* __restrict__ acc) {
@@ -403,13 +404,13 @@ __global__ __launch_bounds__(kLaneB) void k_census_totals(const uint32_t* __rest
         slot_bins hs{sbins};
         for (uint64_t base = (uint64_t)blockIdx.x * kLaneB * kTotalsPer; base < U;
              base += (uint64_t)gridDim.x * kLaneB * kTotalsPer)
-            totals_entries<kTotalsPer, kLaneB>(base, U, nbr, owner, row_ptr, tpre, n, TS, hs);
+            totals_entries<kTotalsPer, kLaneB>(base, U, nbr, owner, rinfo, tpre, n, TS, hs);
         global_bins g{acc};
         slots_flush(sbins, bin_of_slot, nslots, g);
     } else {
         for (uint64_t base = (uint64_t)blockIdx.x * kLaneB * kTotalsPer; base < U;
              base += (uint64_t)gridDim.x * kLaneB * kTotalsPer)
-            totals_entries<kTotalsPer, kLaneB>(base, U, nbr, owner, row_ptr, tpre, n, T, hw);
+            totals_entries<kTotalsPer, kLaneB>(base, U, nbr, owner, rinfo, tpre, n, T, hw);
         hw.flush(acc);
     }
 }
@@ -1221,12 +1222,12 @@ __global__ __launch_bounds__(kBatchB) void k_census_batch(const graph_desc* __re
                 __syncthreads();
                 slot_bins hs{sbins};
                 for (uint32_t b0 = it.begin; b0 < it.end; b0 += kTotalsPer * kBatchB)
-                    totals_entries<kTotalsPer, kBatchB>(b0, it.end, g.nbr, g.owner, g.row_ptr, g.tpre, g.n, TS,
+                    totals_entries<kTotalsPer, kBatchB>(b0, it.end, g.nbr, g.owner, g.rinfo, g.tpre, g.n, TS,
                                                         hs);
                 slots_flush(sbins, bin_of_slot, nslots, h);
             } else {
                 for (uint32_t b0 = it.begin; b0 < it.end; b0 += kTotalsPer * kBatchB)
-                    totals_entries<kTotalsPer, kBatchB>(b0, it.end, g.nbr, g.owner, g.row_ptr, g.tpre, g.n, T, h);
+                    totals_entries<kTotalsPer, kBatchB>(b0, it.end, g.nbr, g.owner, g.rinfo, g.tpre, g.n, T, h);
             }
         }
         else if (it.kind & kItemTri)
@@ -1313,7 +1314,7 @@ hipError_t census_launch(const device_graph& g, const census_slices& sl, bool tr
         if (g.U > 0) {
             uint32_t grid = (uint32_t)std::min<uint64_t>((g.U + kTotalsPer * kLaneB - 1) / (kTotalsPer * kLaneB),
                                                          cfg.lane_blocks);
-            hipLaunchKernelGGL(k_census_totals, dim3(grid), dim3(kLaneB), 0, s, g.nbr, g.owner, g.row_ptr, g.tpre,
+            hipLaunchKernelGGL(k_census_totals, dim3(grid), dim3(kLaneB), 0, s, g.nbr, g.owner, g.rinfo, g.tpre,
                                g.U, (uint64_t)g.n, table, acc);
         }
         if (ev) (void)hipEventRecord(ev[2 * kBuckets + 1], s);

@@ -74,6 +74,9 @@ def check(ctx, n, src, dst, want=None, modes=MODES, name=""):
             idx = {"lane": 0, "wave": 1, "group": 2, "hub": 3}[mode]
             total = sum(info["bucket_dyads"])
             assert info["bucket_dyads"][idx] == total, (mode, info["bucket_dyads"])
+        # hub tasks form groups of at most eight consecutive tasks
+        for tasks, groups in (("hub_tasks", "hub_groups"), ("tri_tasks", "tri_groups")):
+            assert -(-info[tasks] // 8) <= info[groups] <= info[tasks], (mode, info[tasks], info[groups])
         if mode.startswith("tri"):
             assert info["fwd_entries"] == info["asym_dyads"] + info["mutual_dyads"], (mode, info)
             if mode != "tri" and sum(info["tri_bucket_edges"]):

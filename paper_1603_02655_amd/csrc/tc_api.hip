@@ -74,8 +74,10 @@ void fill_info(const tc_graph_s* g, tc_graph_info* info) {
 int run_census_locked(tc_context_s* ctx, const device_graph& g, const census_slices& sl,
                       unsigned long long raw[16], int table, bool tri) {
     hipEvent_t* ev = ctx->timing ? ctx->ev : nullptr;
-    hipError_t e = census_launch(g, sl, tri, ctx->tables + 64 * table, ctx->acc, ctx->counters,
-                                 config_of(ctx->tuning), ctx->stream, ev);
+    census_config cfg = config_of(ctx->tuning);
+    cfg.side_blocks = (uint32_t)ctx->cu_count;
+    hipError_t e = census_launch(g, sl, tri, ctx->tables + 64 * table, ctx->acc, ctx->counters, cfg, ctx->stream,
+                                 ev, ctx->side, ctx->fork);
     if (e == hipSuccess)
         e = hipMemcpyAsync(ctx->host_raw, ctx->acc, sizeof(unsigned long long) * kNumClasses,
                            hipMemcpyDeviceToHost, ctx->stream);
@@ -222,6 +224,8 @@ int tc_context_create(int device, uint64_t hbm_budget_bytes, void* hip_stream, t
         e = hipMemcpy(ctx->tables, host, sizeof(host), hipMemcpyHostToDevice);
     }
     for (int i = 0; i < 2 * kBuckets + 2 && e == hipSuccess; ++i) e = hipEventCreate(&ctx->ev[i]);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking);
+    for (int i = 0; i < 2 && e == hipSuccess; ++i) e = hipEventCreateWithFlags(&ctx->fork[i], hipEventDisableTiming);
     if (e == hipSuccess) {
         size_t free_b = 0, total_b = 0;
         e = hipMemGetInfo(&free_b, &total_b);
@@ -256,8 +260,12 @@ int tc_context_destroy(tc_context ctx) {
         ctx->graphs.clear();
     }
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    if (ctx->side) (void)hipStreamSynchronize(ctx->side);
     for (int i = 0; i < 2 * kBuckets + 2; ++i)
         if (ctx->ev[i]) (void)hipEventDestroy(ctx->ev[i]);
+    for (int i = 0; i < 2; ++i)
+        if (ctx->fork[i]) (void)hipEventDestroy(ctx->fork[i]);
+    if (ctx->side) (void)hipStreamDestroy(ctx->side);
     if (ctx->acc) (void)hipFree(ctx->acc);
     if (ctx->tables) (void)hipFree(ctx->tables);
     if (ctx->counters) (void)hipFree(ctx->counters);

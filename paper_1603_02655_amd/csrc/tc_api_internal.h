@@ -38,6 +38,8 @@ struct tc_context_s {
     uint8_t* tables = nullptr;          // 4 x 64 bin indices (device): the 16-class table,
                                         // then the labelled census's pass tables for f_uv = 1, 2, 3
     hipEvent_t ev[2 * tc::kBuckets + 2] = {};
+    hipStream_t side = nullptr;         // runs the totals pass beside the bucket kernels
+    hipEvent_t fork[2] = {};            // side stream start / end
     bool timing = false;
     tc_kernel_stats kstats{};
     tc_tuning tuning{};

@@ -9,6 +9,7 @@ struct census_config {
     uint32_t wave_blocks = 8192;    // resident one-wave workgroups of the wave kernel
     uint32_t group_blocks = 1024;   // resident workgroups of the group kernel
     uint32_t hub_blocks = 1024;     // resident workgroups of the hub kernel
+    uint32_t side_blocks = 256;     // workgroups of the totals pass when it runs on the side stream
 };
 
 // Per-bucket dyad slices [begin, end) into g.dyads (merge buckets); the hub
@@ -62,10 +63,13 @@ hipError_t census_upload_table();
 // kernels over the given slices with `table` (64 bytes of device memory: the
 // bin of every code, kNumClasses for codes that are not counted).  With `tri`
 // the slices index the forward-list edge records (g.tri.edges) and a totals
-// pass over every dyad record runs first.  ev, when not null, holds
+// pass over every dyad record runs too: first on s, or, when `side` is given
+// (with two events in `fork`) and the hub bucket streams more entries than the
+// graph has, on `side` with side_blocks workgroups, followed there by the lane
+// bucket, beside the other bucket kernels; s waits for it at the end.  ev, when not null, holds
 // 2*kBuckets + 2 events: around each bucket's launch, then around the totals.
 hipError_t census_launch(const device_graph& g, const census_slices& sl, bool tri, const uint8_t* table,
                          unsigned long long* acc, unsigned int* counters, const census_config& cfg, hipStream_t s,
-                         hipEvent_t* ev);
+                         hipEvent_t* ev, hipStream_t side = nullptr, hipEvent_t* fork = nullptr);
 
 }  // namespace tc

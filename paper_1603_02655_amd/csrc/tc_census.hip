@@ -1301,7 +1301,7 @@ void launch_hub(const census_args& L, const hub_task* tasks, uint32_t ntasks, ui
 
 hipError_t census_launch(const device_graph& g, const census_slices& sl, bool tri, const uint8_t* table,
                          unsigned long long* acc, unsigned int* counters, const census_config& cfg, hipStream_t s,
-                         hipEvent_t* ev) {
+                         hipEvent_t* ev, hipStream_t side, hipEvent_t* fork) {
     hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, acc, kNumClasses);
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, counters, kBuckets * kXcds);
     const dyad_rec* recs = tri ? g.tri.edges.recs : g.dyads;
@@ -1309,20 +1309,34 @@ hipError_t census_launch(const device_graph& g, const census_slices& sl, bool tr
     const hub_task* tasks = tri ? g.tri.edges.tasks : g.hub_tasks;
     const uint32_t ntasks = tri ? g.tri.edges.n_tasks : g.n_hub_tasks;
     const uint32_t ngroups = tri ? g.tri.edges.n_groups : g.n_hub_groups;
+    // (only when the hub kernel has more to stream than the totals pass)
+    const bool beside = tri && side != nullptr && fork != nullptr && g.tri.edges.stream > g.U;
     if (tri) {
-        if (ev) (void)hipEventRecord(ev[2 * kBuckets], s);
+        // The totals pass (and the lane bucket after it) wait on memory and
+        // the hub kernel on instruction issue: beside it, they use what the
+        // hub kernel leaves.
+        hipStream_t ts = s;
+        if (beside) {
+            hipError_t e = hipEventRecord(fork[0], s);
+            if (e == hipSuccess) e = hipStreamWaitEvent(side, fork[0], 0);
+            if (e != hipSuccess) return e;
+            ts = side;
+        }
+        if (ev) (void)hipEventRecord(ev[2 * kBuckets], ts);
         if (g.U > 0) {
             uint32_t grid = (uint32_t)std::min<uint64_t>((g.U + kTotalsPer * kLaneB - 1) / (kTotalsPer * kLaneB),
-                                                         cfg.lane_blocks);
-            hipLaunchKernelGGL(k_census_totals, dim3(grid), dim3(kLaneB), 0, s, g.nbr, g.owner, g.rinfo, g.tpre,
+                                                         beside ? cfg.side_blocks : cfg.lane_blocks);
+            hipLaunchKernelGGL(k_census_totals, dim3(grid), dim3(kLaneB), 0, ts, g.nbr, g.owner, g.rinfo, g.tpre,
                                g.U, (uint64_t)g.n, table, acc);
         }
-        if (ev) (void)hipEventRecord(ev[2 * kBuckets + 1], s);
+        if (ev) (void)hipEventRecord(ev[2 * kBuckets + 1], ts);
     }
     for (int b = 0; b < kBuckets; ++b) {
         uint64_t cnt = sl.end[b] > sl.begin[b] ? sl.end[b] - sl.begin[b] : 0;
         if (b == kBucketHub) cnt = ntasks;
-        if (ev) (void)hipEventRecord(ev[2 * b], s);
+        // beside the hub kernel, the lane bucket follows the totals pass on the side stream
+        const hipStream_t bs = beside && b == 0 ? side : s;
+        if (ev) (void)hipEventRecord(ev[2 * b], bs);
         if (cnt > 0) {
             census_args L{recs + sl.begin[b], (uint32_t)cnt, nbr, g.tpre, (uint64_t)g.n, acc, sl.u_lo, sl.u_hi,
                           table};
@@ -1331,12 +1345,17 @@ hipError_t census_launch(const device_graph& g, const census_slices& sl, bool tr
                 if (tri) launch_hub<true>(L, tasks, ntasks, ngroups, cfg, counters, s);
                 else launch_hub<false>(L, tasks, ntasks, ngroups, cfg, counters, s);
             } else if (tri) {
-                launch_bucket<true>(b, L, cnt, cfg, counters, s);
+                launch_bucket<true>(b, L, cnt, cfg, counters, bs);
             } else {
-                launch_bucket<false>(b, L, cnt, cfg, counters, s);
+                launch_bucket<false>(b, L, cnt, cfg, counters, bs);
             }
         }
-        if (ev) (void)hipEventRecord(ev[2 * b + 1], s);
+        if (ev) (void)hipEventRecord(ev[2 * b + 1], bs);
+    }
+    if (beside) {
+        hipError_t e = hipEventRecord(fork[1], side);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s, fork[1], 0);
+        if (e != hipSuccess) return e;
     }
     return hipGetLastError();
 }

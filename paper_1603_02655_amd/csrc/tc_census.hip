@@ -21,9 +21,9 @@
 //   lane  : one lane per record, the two rows compared 8 entries at a time;
 //   wave  : one 64-lane wavefront per record, merge path over LDS-staged tiles;
 //   group : one 256-lane workgroup per record, merge path over larger tiles;
-//   hub   : one workgroup per run of records that share an endpoint (anchor),
-//           whose row is staged in an LDS hash table and probed by the other
-//           rows.
+//   hub   : one workgroup per group of runs of records that share an
+//           endpoint (anchor), whose rows are staged in an LDS hash table and
+//           probed by the other rows.
 // The same kernels run over the dyad records (Tri = false) or over the
 // forward-list edge records (Tri = true), where a shared vertex closes a
 // triangle that is credited to its three dyads (on_triangle) and the per-dyad
@@ -690,7 +690,7 @@ __device__ inline void block_scan_u32(uint32_t* a, uint32_t count, uint32_t* wsu
 // the census depends only on the direction bits f = f_uv, fa = f_uw, fb = f_vw
 // (each 1, 2 or 3: the pairs are joined) and on where w lies: below u, between
 // u and v, or above v.  The hub mode counts shared vertices per such signature
-// (81 of them) in one 32-bit LDS histogram per wavefront and turns the counts
+// (81 of them) in one 32-bit LDS histogram per workgroup and turns the counts
 // into class updates when it flushes.
 constexpr uint32_t kSigs = 81;
 
@@ -1070,8 +1070,8 @@ __global__ __launch_bounds__(kHubB) __attribute__((amdgpu_waves_per_eu(7, 7))) v
 
 // --------------------------------------------------------------- batch ----
 // Two persistent launches over the work items of many resident graphs: the
-// hub tasks of every graph (k_census_batch_hub, eight wavefronts per SIMD like
-// the single-graph hub kernel), then the other items (k_census_batch).  A
+// hub task groups of every graph (k_census_batch_hub, seven wavefronts per SIMD
+// like the single-graph hub kernel), then the other items (k_census_batch).  A
 // workgroup takes items one at a time (per-XCD counters); an item is a slice
 // of one graph's bucket, over its dyad records or its forward-list edge
 // records: up to 256 lane-mode records (one per thread), up to

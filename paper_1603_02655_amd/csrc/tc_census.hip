@@ -782,12 +782,11 @@ __device__ inline void hub_bins_flush(const hub_lds& S, const uint8_t* T, H& h) 
 // unless the group is a single task.  Per tile of the members' concatenated
 // anchor rows: clear and fill the hash table (an entry of member m is stored
 // with m above its 25 bits, so each record matches its own anchor only);
-// count, for every record, the entries of the other row that fall in the
-// tile's vertex range; scan the counts; then each wavefront probes a quarter of
-// the flattened (record, entry) list, 64 adjacent entries per gather and
-// kHubGather gathers in flight, and probes the entries that pass the tile's
-// filter 64 at a time.  A hit adds one to the workgroup's count of the hit's
-// signature.
+// count, for every record, the aligned blocks of kHubGather entries that hold
+// the entries of the other row in the tile's vertex range; scan the counts;
+// then each wavefront walks a quarter of the flattened block list, one block
+// per lane, and probes the entries that pass the tile's filter 64 at a time.
+// A hit adds one to the workgroup's count of the hit's signature.
 template <bool Tri, class H>
 __device__ inline void hub_group_run(uint32_t js, uint32_t M, const dyad_rec* __restrict__ dyads,
                                      const uint32_t* __restrict__ nbr, const uint64_t* __restrict__ tpre, uint64_t n,

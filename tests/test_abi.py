@@ -64,3 +64,32 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(tc, "LIB_PATH", str(tmp_path / "absent.so"))
     with pytest.raises(ImportError):
         tc.load()
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """Every field of the binding's structures sits at the offset the C
+    compiler gives it in include/tc.h, and the sizes agree."""
+    structs = {name: getattr(tc, name) for name in ("tc_graph_info", "tc_tuning", "tc_kernel_stats",
+                                                    "tc_serve_stats")}
+    lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "tc.h"', "int main(void) {"]
+    for name, cls in structs.items():
+        lines.append(f'    printf("{name} size %zu\\n", sizeof({name}));')
+        for field, _ in cls._fields_:
+            lines.append(f'    printf("{name} {field} %zu\\n", offsetof({name}, {field}));')
+    lines += ["    return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    import subprocess
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    seen = 0
+    for line in out:
+        if not line:
+            continue
+        name, key, value = line.split()
+        cls = structs[name]
+        got = ctypes.sizeof(cls) if key == "size" else getattr(cls, key).offset
+        assert got == int(value), (name, key, got, value)
+        seen += 1
+    assert seen == sum(len(c._fields_) + 1 for c in structs.values())

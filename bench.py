@@ -306,6 +306,34 @@ def copy_calibration(nbytes: int):
     h.hipFree(b)
 
 
+def copy_bandwidth(nbytes: int = 1 << 30) -> float:
+    """Device-to-device copy rate in GB/s (bytes read + bytes written over the
+    time of three copies after one untimed), the practical HBM rate the
+    census kernels' byte rates are also compared with."""
+    import ctypes
+    from paper_1603_02655_amd import tc
+    h = tc.hip_runtime()
+    a, b = ctypes.c_void_p(), ctypes.c_void_p()
+    if h.hipMalloc(ctypes.byref(a), nbytes) != 0 or h.hipMalloc(ctypes.byref(b), nbytes) != 0:
+        raise MemoryError("hipMalloc failed")
+    try:
+        h.hipMemset.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_size_t]
+        h.hipMemset(a, 1, nbytes)
+        if h.hipMemcpy(b, a, nbytes, 3) != 0:
+            raise RuntimeError("hipMemcpy failed")
+        tc.device_synchronize(0)
+        t = time.perf_counter()
+        for _ in range(3):
+            if h.hipMemcpy(b, a, nbytes, 3) != 0:   # device to device
+                raise RuntimeError("hipMemcpy failed")
+        tc.device_synchronize(0)
+        el = time.perf_counter() - t
+    finally:
+        h.hipFree(a)
+        h.hipFree(b)
+    return 3 * 2 * nbytes / el / 1e9
+
+
 def cpu_tuned(g0, m_kept: int) -> dict:
     """The multicore CPU census of the same method (libtc_cpu.so: per-dyad
     merge with typed counts, task queues, local census per thread) on the whole
@@ -424,8 +452,11 @@ def main():
     ctx.set_timing(True)
     tc.device_synchronize(0)
     t0 = time.perf_counter()
+    step_ms = []
     for i in range(args.steps):
-        counts = ctx.census(g)
+        ts = time.perf_counter()
+        counts = ctx.census(g)                      # returns after the counts are on the host
+        step_ms.append(1000.0 * (time.perf_counter() - ts))
     tc.device_synchronize(0)
     el = time.perf_counter() - t0
     ctx.set_timing(False)
@@ -490,6 +521,8 @@ def main():
         "path": "forward-list triangles" if tri else "dyad intersections",
         "kernels_ms": per_launch_ms,
         "kernel_bytes": bytes_of,
+        "step_ms": {"p10": float(np.percentile(step_ms, 10)), "p50": float(np.percentile(step_ms, 50)),
+                    "p90": float(np.percentile(step_ms, 90))},
         "b_alg_gb": b_alg / 1e9,
         "census_gbs_alg": b_alg / (el / args.steps) / 1e9,
         "build_s": build_s,
@@ -498,6 +531,11 @@ def main():
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
         line["copy_calibration_bytes"] = args.copy_calibration
+    else:
+        # the same kernel rate against a measured device copy
+        bw = copy_bandwidth()
+        line["roofline"]["copy_gbs"] = bw
+        line["roofline"]["frac_of_copy"] = achieved / bw
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")
         line["cpu_baseline"] = cpu_baseline(g0, m_kept, args.cpu_seconds)

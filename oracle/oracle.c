@@ -11,35 +11,41 @@
  *   003, 012, 102, 021D, 021U, 021C, 111D, 111U, 030T, 030C, 201, 120D, 120U,
  *   120C, 210, 300 (here 0-based: class 0 is 003, class 15 is 300).
  *
+ * The census is computed from that definition, not by the thesis's algorithm:
+ * every triple with at least one joined pair is classified once, anchored at
+ * its smallest vertex (triples with one joined pair in bulk per pair), and
+ * class 003 takes the rest of C(n, 3).  It shares no step with the GPU path,
+ * which follows the thesis's per-dyad loop.
+ *
  * Functions and the passages they follow:
  *   oracle_table          the 64 -> 16 isomorphism map (TriadTable).  The thesis
  *                         describes it but does not print it; it is derived here
  *                         from the class definitions by canonical forms under
  *                         the six vertex relabellings.
- *   oracle_census*        the subquadratic census (figure "Subquadratic Triad
- *                         Census Algorithm") with the pre-computed (u, v) dyad
- *                         type of the v0.4 change (figure "Modified TriadCode"),
- *                         IsEdge / IsNeighbour as binary searches in sorted
- *                         out-lists / neighbour lists, S built explicitly.
- *   oracle_census_range   the same loop restricted to canonical dyads whose
- *                         first vertex u lies in [u0, u1): the local census of
- *                         one task queue in the task-queue formulation (figure
- *                         "Subquadratic Triad Census Algorithm based on
- *                         distributed task queues"); class 003 is left at 0.
- *   oracle_census_mt      multithreaded timing variant: canonical dyads split
- *                         into contiguous task queues of equal |N(u)|+|N(v)|-2
- *                         (figure "Canonical Dyad (uniform distr.)" task-queue
- *                         generation), one local census per thread, summed after
- *                         the join (section v0.6, "local census array per thread").
- *   oracle_brute          the naive O(n^3) census the section on the algorithm
- *                         mentions: every triple classified through TriadCode.
+ *   oracle_census         the 16-class census (section "Triad Census
+ *                         Algorithm", the problem statement and the count of
+ *                         null triads as C(n, 3) minus the others).
  *   oracle_census64       the 64-class labelled census the section on the
  *                         TriadCode describes before the table folds it into
- *                         16 classes: the same loop, histogramming the raw
- *                         6-bit code of (u, v, w) in the roles the loop gives
- *                         them; the dyadic term n - |S| - 2 goes to the code of
- *                         the (u, v) pair alone (w joined to neither), and code
- *                         0 is C(n, 3) minus the rest.
+ *                         16 classes: the histogram of the 6-bit code of every
+ *                         triple, read in the roles in which the thesis's loop
+ *                         counts it (u the smallest vertex, v the smaller of the
+ *                         vertices joined to u, w the third; a triple with one
+ *                         joined pair takes the code of that pair alone), and
+ *                         code 0 is C(n, 3) minus the rest.
+ *   oracle_census_range   classes 1..15 of the triples whose smallest vertex
+ *                         (for one joined pair: the pair's smaller vertex) lies
+ *                         in [x0, x1): what one task queue of canonical dyads
+ *                         with first vertex in that range counts in the
+ *                         task-queue formulation (figure "Subquadratic Triad
+ *                         Census Algorithm based on distributed task queues");
+ *                         class 003 is left at 0.
+ *   oracle_census_mt      the same census with threads taking chunks of
+ *                         smallest vertices, one local histogram per thread,
+ *                         summed after the join (timing variant).
+ *   oracle_brute          the naive O(n^3) census the section on the algorithm
+ *                         mentions: every triple classified through TriadCode
+ *                         over an n x n bit matrix.
  *
  * Input handling (reading of the thesis's "strict digraph, E a set"): arcs
  * (u, u) are dropped and repeated arcs are merged; ids must lie in [0, n).
@@ -137,7 +143,8 @@ int oracle_table(uint8_t T[64])
 }
 
 /* ------------------------------------------------------------------ */
-/* Graph: sorted out-lists (IsEdge) and sorted neighbour lists (N)     */
+/* Graph: sorted out-lists (arcs) and sorted neighbour lists with the  */
+/* direction of every joined pair                                      */
 /* ------------------------------------------------------------------ */
 
 typedef struct {
@@ -147,6 +154,7 @@ typedef struct {
     int32_t *out;          /* sorted heads per tail */
     int64_t *nb_ptr;       /* n + 1 */
     int32_t *nb;           /* sorted undirected neighbours per vertex */
+    uint8_t *nb_dir;       /* per neighbour entry w of x: bit0 x->w, bit1 w->x */
     uint8_t T[64];
 } og_t;
 
@@ -154,6 +162,22 @@ static int cmp_i64(const void *a, const void *b)
 {
     int64_t x = *(const int64_t *)a, y = *(const int64_t *)b;
     return (x > y) - (x < y);
+}
+
+static int in_sorted(const int32_t *a, int64_t len, int32_t x)
+{
+    int64_t lo = 0, hi = len;
+    while (lo < hi) {
+        int64_t mid = lo + (hi - lo) / 2;
+        if (a[mid] < x) lo = mid + 1; else hi = mid;
+    }
+    return lo < len && a[lo] == x;
+}
+
+/* is the arc x -> y in E? */
+static int arc(const og_t *g, int32_t x, int32_t y)
+{
+    return in_sorted(g->out + g->out_ptr[x], g->out_ptr[x + 1] - g->out_ptr[x], y);
 }
 
 /* Builds the oracle's own adjacency.  Returns NULL on a bad id or no memory. */
@@ -197,9 +221,12 @@ void *oracle_graph_new(int32_t n, int64_t m, const int32_t *src, const int32_t *
         if (i == 0 || ukey[i] != ukey[i - 1]) ukey[b++] = ukey[i];
     g->nb_ptr = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
     g->nb = (int32_t *)malloc(sizeof(int32_t) * (size_t)(b > 0 ? b : 1));
+    g->nb_dir = (uint8_t *)malloc((size_t)(b > 0 ? b : 1));
     for (int64_t i = 0; i < b; ++i) {
-        g->nb_ptr[ukey[i] / n + 1]++;
-        g->nb[i] = (int32_t)(ukey[i] % n);
+        int32_t x = (int32_t)(ukey[i] / n), w = (int32_t)(ukey[i] % n);
+        g->nb_ptr[x + 1]++;
+        g->nb[i] = w;
+        g->nb_dir[i] = (uint8_t)(arc(g, x, w) | (arc(g, w, x) << 1));
     }
     for (int32_t u = 0; u < n; ++u) g->nb_ptr[u + 1] += g->nb_ptr[u];
     free(key);
@@ -211,7 +238,7 @@ void oracle_graph_free(void *h)
 {
     og_t *g = (og_t *)h;
     if (!g) return;
-    free(g->out_ptr); free(g->out); free(g->nb_ptr); free(g->nb); free(g);
+    free(g->out_ptr); free(g->out); free(g->nb_ptr); free(g->nb); free(g->nb_dir); free(g);
 }
 
 int64_t oracle_graph_arcs(void *h) { return ((og_t *)h)->arcs; }
@@ -223,233 +250,214 @@ int64_t oracle_graph_degree(void *h, int32_t u)
     return g->nb_ptr[u + 1] - g->nb_ptr[u];
 }
 
-static int in_sorted(const int32_t *a, int64_t len, int32_t x)
+/* ------------------------------------------------------------------ */
+/* The census by its definition: every triple classified once          */
+/* ------------------------------------------------------------------ */
+
+/* Per-thread look-up tables over the vertices.  in_x[w] == x + 1 exactly when
+ * w is joined to x, and then dir_x[w] holds the arcs between them (bit0 x->w,
+ * bit1 w->x); in_p / dir_p do the same for the second vertex p of the current
+ * pair, keyed by that pair's entry position + 1 so no table is ever cleared. */
+typedef struct {
+    int64_t *in_x, *in_p;
+    uint8_t *dir_x, *dir_p;
+} ws_t;
+
+static int ws_init(ws_t *ws, int32_t n)
 {
-    int64_t lo = 0, hi = len;
-    while (lo < hi) {
-        int64_t mid = lo + (hi - lo) / 2;
-        if (a[mid] < x) lo = mid + 1; else hi = mid;
+    size_t len = (size_t)(n > 0 ? n : 1);
+    ws->in_x = (int64_t *)calloc(len, sizeof(int64_t));
+    ws->in_p = (int64_t *)calloc(len, sizeof(int64_t));
+    ws->dir_x = (uint8_t *)calloc(len, 1);
+    ws->dir_p = (uint8_t *)calloc(len, 1);
+    return ws->in_x && ws->in_p && ws->dir_x && ws->dir_p ? 0 : -1;
+}
+
+static void ws_free(ws_t *ws)
+{
+    free(ws->in_x); free(ws->in_p); free(ws->dir_x); free(ws->dir_p);
+}
+
+/*
+ * Every unordered triple {x, p, q} of distinct vertices with x its smallest
+ * vertex, classified by the 6-bit TriadCode of its induced digraph, read in the
+ * roles u = x, v = p, w = q (bits 1 u->v, 2 v->u, 4 u->w, 8 w->u, 16 v->w,
+ * 32 w->v).  A triple with no joined pair is not visited (code 0 is filled in
+ * by subtraction from C(n, 3)).  The others are met exactly once:
+ *
+ *   one joined pair {x, p}, x < p:  counted in bulk per pair, as the number of
+ *       third vertices joined to neither, n - 2 - |(N(x) u N(p)) \ {x, p}|;
+ *   x joined to both others:        p < q, both in N(x);
+ *   x joined to exactly one other:  p that one, q in N(p) \ N(x), q > x.
+ *
+ * In the last two cases v is the smaller of the vertices joined to u and w
+ * the remaining one, which are the roles in which the subquadratic loop of
+ * section "Triad Census Algorithm" counts the triple (its canonical condition
+ * gives a triple a < b < c to the dyad (a, b) when a, b are joined, else to
+ * (a, c)); a pair's bulk count goes to the code of the pair alone.  The codes
+ * are added into hist[64].
+ */
+static void triples_at(const og_t *g, int32_t x, ws_t *ws, uint64_t hist[64])
+{
+    const int64_t n = g->n;
+    const int64_t xb = g->nb_ptr[x], xe = g->nb_ptr[x + 1];
+    for (int64_t i = xb; i < xe; ++i) {
+        ws->in_x[g->nb[i]] = (int64_t)x + 1;
+        ws->dir_x[g->nb[i]] = g->nb_dir[i];
     }
-    return lo < len && a[lo] == x;
-}
+    for (int64_t i = xb; i < xe; ++i) {
+        const int32_t p = g->nb[i];
+        if (p < x) continue;
+        const int64_t key = i + 1;
+        const int64_t pb = g->nb_ptr[p], pe = g->nb_ptr[p + 1];
+        for (int64_t j = pb; j < pe; ++j) {
+            ws->in_p[g->nb[j]] = key;
+            ws->dir_p[g->nb[j]] = g->nb_dir[j];
+        }
+        const int uv = ws->dir_x[p];                  /* bit0 x->p, bit1 p->x */
 
-/* IsEdge(x, y): is the arc x -> y in E? */
-static int is_edge(const og_t *g, int32_t x, int32_t y)
-{
-    return in_sorted(g->out + g->out_ptr[x], g->out_ptr[x + 1] - g->out_ptr[x], y);
-}
+        /* one joined pair: the third vertices joined to x or to p */
+        int64_t touched = 0;
+        for (int64_t j = xb; j < xe; ++j)
+            if (g->nb[j] != p) ++touched;
+        for (int64_t j = pb; j < pe; ++j) {
+            const int32_t w = g->nb[j];
+            if (w != x && ws->in_x[w] != (int64_t)x + 1) ++touched;
+        }
+        hist[uv] += (uint64_t)(n - 2 - touched);
 
-/* IsNeighbour(x, y): are x and y joined in either direction? */
-static int is_neighbour(const og_t *g, int32_t x, int32_t y)
-{
-    return in_sorted(g->nb + g->nb_ptr[x], g->nb_ptr[x + 1] - g->nb_ptr[x], y);
-}
+        /* x joined to p and to q, p < q */
+        for (int64_t j = xb; j < xe; ++j) {
+            const int32_t q = g->nb[j];
+            if (q <= p) continue;
+            const int pq = ws->in_p[q] == key ? ws->dir_p[q] : 0;
+            hist[uv | ws->dir_x[q] << 2 | pq << 4] += 1;
+        }
 
-/* S = N(u) u N(v) \ {u, v}, written sorted into buf; returns |S|. */
-static int64_t build_S(const og_t *g, int32_t u, int32_t v, int32_t *buf)
-{
-    const int32_t *a = g->nb + g->nb_ptr[u], *b = g->nb + g->nb_ptr[v];
-    int64_t la = g->nb_ptr[u + 1] - g->nb_ptr[u], lb = g->nb_ptr[v + 1] - g->nb_ptr[v];
-    int64_t i = 0, j = 0, s = 0;
-    while (i < la || j < lb) {
-        int32_t x;
-        if (j >= lb || (i < la && a[i] < b[j])) x = a[i++];
-        else if (i >= la || b[j] < a[i]) x = b[j++];
-        else { x = a[i]; ++i; ++j; }
-        if (x != u && x != v) buf[s++] = x;
-    }
-    return s;
-}
-
-/* The per-dyad body: dyad (u, v), u < v, joined in at least one direction. */
-static void census_dyad(const og_t *g, int32_t u, int32_t v, int32_t *buf, uint64_t c[16])
-{
-    int64_t n = g->n;
-    int64_t s = build_S(g, u, v, buf);
-    int e0 = is_edge(g, u, v), e1 = is_edge(g, v, u);
-    int pre = e0 + 2 * e1;                         /* v0.4: (u, v) part of the code */
-    int type = (e0 && e1) ? 2 : 1;                 /* 102 if mutual, else 012 */
-    c[type] += (uint64_t)(n - s - 2);
-    for (int64_t k = 0; k < s; ++k) {
-        int32_t w = buf[k];
-        if (v < w || (w < v && u < w && !is_neighbour(g, u, w))) {
-            int code = pre + 4 * is_edge(g, u, w) + 8 * is_edge(g, w, u)
-                     + 16 * is_edge(g, v, w) + 32 * is_edge(g, w, v);
-            c[g->T[code]] += 1;
+        /* x joined to p only; q joined to p, not to x, q > x */
+        for (int64_t j = pb; j < pe; ++j) {
+            const int32_t q = g->nb[j];
+            if (q <= x || ws->in_x[q] == (int64_t)x + 1) continue;
+            hist[uv | ws->dir_p[q] << 4] += 1;
         }
     }
 }
 
-static int64_t max_degree(const og_t *g)
+static u128 choose3(int64_t n)
 {
-    int64_t d = 0;
-    for (int32_t u = 0; u < g->n; ++u) {
-        int64_t x = g->nb_ptr[u + 1] - g->nb_ptr[u];
-        if (x > d) d = x;
-    }
-    return d;
+    return n >= 3 ? (u128)n * (u128)(n - 1) * (u128)(n - 2) / 6 : 0;
 }
 
-/* canonical dyads with u in [u0, u1); classes 1..15 accumulated into c */
-static void census_vertices(const og_t *g, int32_t u0, int32_t u1, int32_t *buf, uint64_t c[16])
+/* 16-class census from the code histogram: class T[code] takes every code;
+ * class 003 is C(n, 3) minus the other classes when `null` is set, else 0. */
+static void fold(const og_t *g, const uint64_t hist[64], int null, uint64_t out[16])
 {
-    for (int32_t u = u0; u < u1; ++u)
-        for (int64_t p = g->nb_ptr[u]; p < g->nb_ptr[u + 1]; ++p) {
-            int32_t v = g->nb[p];
-            if (u < v) census_dyad(g, u, v, buf, c);
-        }
-}
-
-/* C(n, 3) - sum of the other 15 classes, with a 128-bit product. */
-static void finish_null(int64_t n, uint64_t c[16])
-{
-    u128 total = n >= 3 ? (u128)n * (u128)(n - 1) * (u128)(n - 2) / 6 : 0;
+    uint64_t c[16] = {0};
     u128 sum = 0;
-    for (int k = 1; k < 16; ++k) sum += c[k];
-    c[0] = (uint64_t)(total - sum);
+    for (int code = 1; code < 64; ++code) {
+        c[g->T[code]] += hist[code];
+        sum += hist[code];
+    }
+    c[0] = null ? (uint64_t)(choose3(g->n) - sum) : 0;
+    memcpy(out, c, sizeof(c));
+}
+
+static int hist_range(const og_t *g, int32_t x0, int32_t x1, uint64_t hist[64])
+{
+    ws_t ws;
+    if (ws_init(&ws, g->n) != 0) { ws_free(&ws); return -1; }
+    for (int32_t x = x0; x < x1; ++x) triples_at(g, x, &ws, hist);
+    ws_free(&ws);
+    return 0;
 }
 
 int oracle_census(void *h, uint64_t out[16])
 {
     og_t *g = (og_t *)h;
-    uint64_t c[16] = {0};
-    int32_t *buf = (int32_t *)malloc(sizeof(int32_t) * (size_t)(2 * max_degree(g) + 1));
-    if (!buf) return -1;
-    census_vertices(g, 0, g->n, buf, c);
-    free(buf);
-    finish_null(g->n, c);
-    memcpy(out, c, sizeof(c));
+    uint64_t hist[64] = {0};
+    if (hist_range(g, 0, g->n, hist) != 0) return -1;
+    fold(g, hist, 1, out);
     return 0;
 }
 
-/* The per-dyad body again, counting raw codes instead of classes. */
-static void census64_dyad(const og_t *g, int32_t u, int32_t v, int32_t *buf, uint64_t c[64])
-{
-    int64_t n = g->n;
-    int64_t s = build_S(g, u, v, buf);
-    int e0 = is_edge(g, u, v), e1 = is_edge(g, v, u);
-    int pre = e0 + 2 * e1;
-    c[pre] += (uint64_t)(n - s - 2);
-    for (int64_t k = 0; k < s; ++k) {
-        int32_t w = buf[k];
-        if (v < w || (w < v && u < w && !is_neighbour(g, u, w))) {
-            int code = pre + 4 * is_edge(g, u, w) + 8 * is_edge(g, w, u)
-                     + 16 * is_edge(g, v, w) + 32 * is_edge(g, w, v);
-            c[code] += 1;
-        }
-    }
-}
-
+/* 64-class labelled census: the code histogram itself, code 0 (no joined pair)
+ * being C(n, 3) minus the rest. */
 int oracle_census64(void *h, uint64_t out[64])
 {
     og_t *g = (og_t *)h;
-    uint64_t c[64] = {0};
-    int32_t *buf = (int32_t *)malloc(sizeof(int32_t) * (size_t)(2 * max_degree(g) + 1));
-    if (!buf) return -1;
-    for (int32_t u = 0; u < g->n; ++u)
-        for (int64_t p = g->nb_ptr[u]; p < g->nb_ptr[u + 1]; ++p) {
-            int32_t v = g->nb[p];
-            if (u < v) census64_dyad(g, u, v, buf, c);
-        }
-    free(buf);
-    int64_t n = g->n;
-    u128 total = n >= 3 ? (u128)n * (u128)(n - 1) * (u128)(n - 2) / 6 : 0;
+    uint64_t hist[64] = {0};
+    if (hist_range(g, 0, g->n, hist) != 0) return -1;
     u128 sum = 0;
-    for (int k = 1; k < 64; ++k) sum += c[k];
-    c[0] = (uint64_t)(total - sum);
-    memcpy(out, c, sizeof(c));
+    for (int code = 1; code < 64; ++code) sum += hist[code];
+    hist[0] = (uint64_t)(choose3(g->n) - sum);
+    memcpy(out, hist, sizeof(hist));
     return 0;
 }
 
-int oracle_census_range(void *h, int32_t u0, int32_t u1, uint64_t out[16])
+/* Classes 1..15 of the triples whose smallest vertex lies in [x0, x1) (a
+ * triple with one joined pair: the smaller vertex of that pair); class 003
+ * is left at 0.  The parts of a partition of [0, n) add up to the census. */
+int oracle_census_range(void *h, int32_t x0, int32_t x1, uint64_t out[16])
 {
     og_t *g = (og_t *)h;
-    if (u0 < 0) u0 = 0;
-    if (u1 > g->n) u1 = g->n;
-    uint64_t c[16] = {0};
-    int32_t *buf = (int32_t *)malloc(sizeof(int32_t) * (size_t)(2 * max_degree(g) + 1));
-    if (!buf) return -1;
-    if (u0 < u1) census_vertices(g, u0, u1, buf, c);
-    free(buf);
-    memcpy(out, c, sizeof(c));
+    if (x0 < 0) x0 = 0;
+    if (x1 > g->n) x1 = g->n;
+    uint64_t hist[64] = {0};
+    if (x0 < x1 && hist_range(g, x0, x1, hist) != 0) return -1;
+    fold(g, hist, 0, out);
     return 0;
 }
 
-/* ---- multithreaded variant: task queues of equal |N(u)|+|N(v)|-2 ---- */
+/* ---- multithreaded variant: threads take chunks of smallest vertices ---- */
 
 typedef struct {
     const og_t *g;
-    int32_t u_begin, u_end;     /* vertex range of the first dyad's u .. */
-    int64_t p_begin, p_end;     /* .. and the neighbour-entry range it spans */
-    uint64_t c[16];
-} task_t;
+    int32_t *next;              /* shared: first vertex of the next chunk */
+    int32_t chunk;
+    int err;
+    uint64_t hist[64];
+} mt_t;
 
-static void *task_run(void *arg)
+static void *mt_run(void *arg)
 {
-    task_t *t = (task_t *)arg;
-    const og_t *g = t->g;
-    int32_t *buf = (int32_t *)malloc(sizeof(int32_t) * (size_t)(2 * max_degree(g) + 1));
-    if (!buf) return (void *)1;
-    memset(t->c, 0, sizeof(t->c));
-    /* dyads are the neighbour entries p of u with u < nb[p], taken in order */
-    int32_t u = t->u_begin;
-    for (int64_t p = t->p_begin; p < t->p_end; ++p) {
-        while (p >= g->nb_ptr[u + 1]) ++u;
-        int32_t v = g->nb[p];
-        if (u < v) census_dyad(g, u, v, buf, t->c);
+    mt_t *t = (mt_t *)arg;
+    ws_t ws;
+    if (ws_init(&ws, t->g->n) != 0) { ws_free(&ws); t->err = 1; return NULL; }
+    for (;;) {
+        int32_t x0 = __atomic_fetch_add(t->next, t->chunk, __ATOMIC_RELAXED);
+        if (x0 >= t->g->n) break;
+        int32_t x1 = x0 + t->chunk < t->g->n ? x0 + t->chunk : t->g->n;
+        for (int32_t x = x0; x < x1; ++x) triples_at(t->g, x, &ws, t->hist);
     }
-    free(buf);
+    ws_free(&ws);
     return NULL;
 }
 
+/* Same result as oracle_census; returns the number of threads used. */
 int oracle_census_mt(void *h, int threads, uint64_t out[16])
 {
     og_t *g = (og_t *)h;
     if (threads < 1) threads = 1;
-    /* total uniform-distribution workload */
-    int64_t total = 0;
-    for (int32_t u = 0; u < g->n; ++u)
-        for (int64_t p = g->nb_ptr[u]; p < g->nb_ptr[u + 1]; ++p) {
-            int32_t v = g->nb[p];
-            if (u < v) total += (g->nb_ptr[u + 1] - g->nb_ptr[u]) + (g->nb_ptr[v + 1] - g->nb_ptr[v]) - 2;
-        }
-    int64_t quota = total / threads + 1;
-    task_t *tasks = (task_t *)calloc((size_t)threads, sizeof(task_t));
+    int32_t next = 0;
+    mt_t *t = (mt_t *)calloc((size_t)threads, sizeof(mt_t));
     pthread_t *tid = (pthread_t *)calloc((size_t)threads, sizeof(pthread_t));
-    int q = 0;
-    int64_t load = 0;
-    tasks[0].g = g; tasks[0].u_begin = 0; tasks[0].p_begin = 0;
-    for (int32_t u = 0; u < g->n; ++u)
-        for (int64_t p = g->nb_ptr[u]; p < g->nb_ptr[u + 1]; ++p) {
-            int32_t v = g->nb[p];
-            if (!(u < v)) continue;
-            load += (g->nb_ptr[u + 1] - g->nb_ptr[u]) + (g->nb_ptr[v + 1] - g->nb_ptr[v]) - 2;
-            if (load > quota && q + 1 < threads) {     /* close this queue after dyad p */
-                tasks[q].p_end = p + 1;
-                ++q;
-                tasks[q].g = g;
-                tasks[q].u_begin = u;
-                tasks[q].p_begin = p + 1;
-                load = 0;
-            }
-        }
-    tasks[q].p_end = g->nb_ptr[g->n];
-    int nq = q + 1;
-    for (int i = 0; i < nq; ++i) pthread_create(&tid[i], NULL, task_run, &tasks[i]);
-    int err = 0;
-    uint64_t c[16] = {0};
-    for (int i = 0; i < nq; ++i) {
-        void *r = NULL;
-        pthread_join(tid[i], &r);
-        if (r) err = 1;
-        for (int k = 0; k < 16; ++k) c[k] += tasks[i].c[k];
+    if (!t || !tid) { free(t); free(tid); return -1; }
+    for (int i = 0; i < threads; ++i) {
+        t[i].g = g; t[i].next = &next; t[i].chunk = 64;
+        pthread_create(&tid[i], NULL, mt_run, &t[i]);
     }
-    free(tasks);
+    uint64_t hist[64] = {0};
+    int err = 0;
+    for (int i = 0; i < threads; ++i) {
+        pthread_join(tid[i], NULL);
+        err |= t[i].err;
+        for (int k = 0; k < 64; ++k) hist[k] += t[i].hist[k];
+    }
+    free(t);
     free(tid);
     if (err) return -1;
-    finish_null(g->n, c);
-    memcpy(out, c, sizeof(c));
-    return nq;
+    fold(g, hist, 1, out);
+    return threads;
 }
 
 /* ---- naive O(n^3) census over an n x n bit matrix ---- */

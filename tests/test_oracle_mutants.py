@@ -1,7 +1,8 @@
 """Planted mistakes in copies of the oracle must be caught by the pins.
 
-Each mutant is a text edit of oracle.c (a dropped negation, an off-by-one, a
-transposed operand, ...) compiled into a temporary library on the CPU.  The
+Each mutant is a text edit of oracle.c (a dropped condition, an off-by-one, a
+transposed operand, a stale look-up, ...) compiled into a temporary library on
+the CPU.  The
 test asserts that at least one independent pin (rule-based Python brute force,
 the thesis's worked example, the degree identities) rejects it.
 """
@@ -19,17 +20,21 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(os.path.dirname(HERE), "oracle", "oracle.c")
 
 MUTANTS = {
-    "drop-not-neighbour": ("&& !is_neighbour(g, u, w)", "&& is_neighbour(g, u, w)"),
-    "dyadic-off-by-one": ("(uint64_t)(n - s - 2)", "(uint64_t)(n - s - 1)"),
-    "swap-vw-bits": ("16 * is_edge(g, v, w) + 32 * is_edge(g, w, v)",
-                     "16 * is_edge(g, w, v) + 32 * is_edge(g, v, w)"),
-    "mutual-test-or": ("(e0 && e1) ? 2 : 1", "(e0 || e1) ? 2 : 1"),
-    "canonical-w-gt-u": ("v < w ||", "u < w ||"),
+    "third-vertex-joined-to-x": ("if (q <= x || ws->in_x[q] == (int64_t)x + 1) continue;",
+                                 "if (q <= x) continue;"),
+    "third-vertex-may-be-x": ("if (q <= x || ws->in_x[q] == (int64_t)x + 1) continue;",
+                              "if (q < x || ws->in_x[q] == (int64_t)x + 1) continue;"),
+    "pair-q-equal-p": ("if (q <= p) continue;", "if (q < p) continue;"),
+    "both-orientations": ("if (p < x) continue;\n", "\n"),
+    "single-pair-off-by-one": ("(uint64_t)(n - 2 - touched)", "(uint64_t)(n - 1 - touched)"),
+    "touched-counts-x": ("if (w != x && ws->in_x[w] != (int64_t)x + 1) ++touched;",
+                         "if (ws->in_x[w] != (int64_t)x + 1) ++touched;"),
+    "stale-p-table": ("ws->in_p[q] == key ? ws->dir_p[q] : 0", "ws->dir_p[q]"),
+    "direction-transposed": ("arc(g, x, w) | (arc(g, w, x) << 1)", "arc(g, w, x) | (arc(g, x, w) << 1)"),
     "null-count": ("(u128)(n - 2) / 6", "(u128)(n - 3) / 6"),
     "no-neighbour-dedup": ("if (i == 0 || ukey[i] != ukey[i - 1]) ukey[b++] = ukey[i];",
                            "ukey[b++] = ukey[i];"),
     "swap-111-labels": ("/* 111D */ {0, 1, 1, 0, 2, 1, -1},", "/* 111D */ {0, 1, 1, 0, 1, 2, -1},"),
-    "keep-u-in-S": ("if (x != u && x != v) buf[s++] = x;", "if (x != v) buf[s++] = x;"),
 }
 
 
@@ -93,14 +98,12 @@ def test_pins_catch_mutant(name):
 # Mistakes planted only in the labelled (64-class) census body: its classes
 # are unchanged by most of them, so the brute force by triples must catch them.
 MUTANTS64 = {
-    "dyadic-term-to-null": ("c[pre] += (uint64_t)(n - s - 2);", "c[0] += (uint64_t)(n - s - 2);"),
-    "uv-pair-transposed": ("int pre = e0 + 2 * e1;\n    c[pre]", "int pre = e1 + 2 * e0;\n    c[pre]"),
-    "u-and-v-roles-swapped": ("int code = pre + 4 * is_edge(g, u, w) + 8 * is_edge(g, w, u)\n"
-                              "                     + 16 * is_edge(g, v, w) + 32 * is_edge(g, w, v);\n"
-                              "            c[code] += 1;",
-                              "int code = pre + 16 * is_edge(g, u, w) + 32 * is_edge(g, w, u)\n"
-                              "                     + 4 * is_edge(g, v, w) + 8 * is_edge(g, w, v);\n"
-                              "            c[code] += 1;"),
+    "dyadic-term-to-null": ("hist[uv] += (uint64_t)(n - 2 - touched);",
+                            "hist[0] += (uint64_t)(n - 2 - touched);"),
+    "uv-pair-transposed": ("const int uv = ws->dir_x[p];",
+                           "const int uv = (ws->dir_x[p] >> 1) | ((ws->dir_x[p] & 1) << 1);"),
+    "u-and-v-roles-swapped": ("hist[uv | ws->dir_p[q] << 4] += 1;",
+                              "hist[(uv >> 1 | (uv & 1) << 1) | ws->dir_p[q] << 2] += 1;"),
 }
 
 

@@ -51,6 +51,9 @@ enum {
 
 enum { TC_NUM_CLASSES = 16, TC_NUM_BUCKETS = 4 };
 
+/* Most graphs one tc_census_each_noalloc call takes. */
+enum { TC_NOALLOC_MAX_GRAPHS = 256 };
+
 /* What the build kept and how the canonical dyads were bucketed. */
 typedef struct {
     int64_t arcs_in;              /* m as passed */
@@ -184,6 +187,24 @@ int tc_census_batch(tc_context ctx, const tc_graph* graphs, int32_t count, uint6
 /* Same result as tc_census_batch, but one tc_census-style launch sequence per
  * graph (the per-graph baseline of the batched mode). */
 int tc_census_each(tc_context ctx, const tc_graph* graphs, int32_t count, uint64_t* counts);
+
+/* For callers that cannot allocate device memory while they run (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same counts as tc_census_each, without any allocation.  The kernels'
+ * scratch (work counters and one block of 16 accumulators per graph) lives in
+ * a fixed device array of the library, 33,024 bytes per GPU, held until the
+ * process ends; the read-back goes through pinned host memory the context
+ * allocated when it was created.  The launches of all graphs are queued back
+ * to back and the counts read once at the end.
+ *   graphs: count resident graphs of ctx (the same graph may repeat);
+ *   counts (host): receives count*16 values, graph i at counts[16*i].
+ * Errors: TC_ERR_ARG (null or unknown handle, count < 0), TC_ERR_RANGE
+ * (count > TC_NOALLOC_MAX_GRAPHS), TC_ERR_DEVICE.  Every context on one GPU
+ * shares that GPU's array, which keeps the last call's contents: calls that
+ * overlap on one GPU (from two contexts, or from two threads) race and may
+ * return wrong counts.  Calls on one context are serialised.  Kernel timing
+ * (tc_set_timing) is not recorded by this call. */
+int tc_census_each_noalloc(tc_context ctx, const tc_graph* graphs, int32_t count, uint64_t* counts);
 
 /* Queues a census of g for the serving loop and returns at once.  The loop
  * admits jobs while their device footprint fits the budget, runs all admitted

@@ -148,7 +148,38 @@ int build_into(int32_t n, int64_t m, const int32_t* src, const int32_t* dst, uin
     return TC_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Scratch of tc_census_each_noalloc: kNoAllocCounterBytes of work counters,
+// then one block of 16 accumulators per graph.  Each GPU holds its own copy of
+// this array; host code never passes its name to a kernel (on the host it is a
+// stand-in, not a device address) but the address hipGetSymbolAddress returns
+// for the current device, looked up once per device by scratch_for_device.
+constexpr size_t kNoAllocCounterBytes = 256;   // 64 work counters (the kernels use kBuckets x 8)
+constexpr size_t kNoAllocBytes =
+    kNoAllocCounterBytes + sizeof(unsigned long long) * kNumClasses * (size_t)TC_NOALLOC_MAX_GRAPHS;
+static_assert(kNoAllocBytes == 33024, "size stated in tc.h");
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
 namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Address of this device's copy of `scratch`; `device` must be current.
+hipError_t scratch_for_device(int device, void** out) {
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void* p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_ptr[device] = p;
+    }
+    *out = g_scratch_ptr[device];
+    return hipSuccess;
+}
 
 // u-range bounds inside the u-major merge buckets (the hub bucket is filtered
 // by the kernel instead).
@@ -212,6 +243,10 @@ int tc_context_create(int device, uint64_t hbm_budget_bytes, void* hip_stream, t
     if (e == hipSuccess) e = hipMalloc((void**)&ctx->acc, sizeof(unsigned long long) * kNumClasses);
     if (e == hipSuccess) e = hipMalloc((void**)&ctx->counters, sizeof(unsigned int) * 64);
     if (e == hipSuccess) e = hipHostMalloc((void**)&ctx->host_raw, sizeof(unsigned long long) * kNumClasses);
+    if (e == hipSuccess)
+        e = hipHostMalloc((void**)&ctx->host_many,
+                          sizeof(unsigned long long) * kNumClasses * (size_t)TC_NOALLOC_MAX_GRAPHS);
+    if (e == hipSuccess) e = scratch_for_device(device, &ctx->scratch);
     if (e == hipSuccess) e = hipMalloc((void**)&ctx->tables, 4 * 64);
     if (e == hipSuccess) {
         // table 0: the 64 -> 16 class map; table f (1..3): code -> code >> 2 for
@@ -270,6 +305,7 @@ int tc_context_destroy(tc_context ctx) {
     if (ctx->tables) (void)hipFree(ctx->tables);
     if (ctx->counters) (void)hipFree(ctx->counters);
     if (ctx->host_raw) (void)hipHostFree(ctx->host_raw);
+    if (ctx->host_many) (void)hipHostFree(ctx->host_many);
     if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;
     return TC_OK;
@@ -410,6 +446,40 @@ int tc_census_each(tc_context ctx, const tc_graph* graphs, int32_t count, uint64
         if (rc != TC_OK) return rc;
         finalize_counts(graphs[i]->g.n, raw, counts + 16 * (size_t)i);
     }
+    return TC_OK;
+}
+
+int tc_census_each_noalloc(tc_context ctx, const tc_graph* graphs, int32_t count, uint64_t* counts) {
+    if (!ctx || count < 0 || (count > 0 && (!graphs || !counts))) return TC_ERR_ARG;
+    if (count > TC_NOALLOC_MAX_GRAPHS) return TC_ERR_RANGE;
+    if (!ctx->scratch || !ctx->host_many) return TC_ERR_DEVICE;
+    if (hipSetDevice(ctx->device) != hipSuccess) return TC_ERR_DEVICE;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    for (int32_t i = 0; i < count; ++i)
+        if (!graphs[i] || !ctx->graphs.count(graphs[i])) return TC_ERR_ARG;
+    if (count == 0) return TC_OK;
+    unsigned int* ctr = reinterpret_cast<unsigned int*>(ctx->scratch);
+    unsigned long long* accs =
+        reinterpret_cast<unsigned long long*>(static_cast<unsigned char*>(ctx->scratch) + kNoAllocCounterBytes);
+    census_config cfg = config_of(ctx->tuning);
+    cfg.side_blocks = (uint32_t)ctx->cu_count;
+    // every graph's launch sequence zeroes its own accumulator block and the
+    // counters before its kernels; the stream orders the graphs
+    hipError_t e = hipSuccess;
+    for (int32_t i = 0; i < count && e == hipSuccess; ++i) {
+        const device_graph& g = graphs[i]->g;
+        const bool tri = ctx->tuning.tri && g.tri.fwd_ptr;
+        e = census_launch(g, full_slices(g, tri), tri, ctx->tables, accs + (size_t)kNumClasses * i, ctr, cfg,
+                          ctx->stream, nullptr, ctx->side, ctx->fork);
+    }
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(ctx->host_many, accs, sizeof(unsigned long long) * kNumClasses * (size_t)count,
+                           hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return status_from_hip(e);
+    for (int32_t i = 0; i < count; ++i)
+        finalize_counts(graphs[i]->g.n, ctx->host_many + (size_t)kNumClasses * i, counts + 16 * (size_t)i);
+    ctx->kstats.census_calls += (uint64_t)count;
     return TC_OK;
 }
 

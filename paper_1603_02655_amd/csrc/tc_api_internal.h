@@ -44,6 +44,8 @@ struct tc_context_s {
     tc_kernel_stats kstats{};
     tc_tuning tuning{};
     std::set<tc_graph> graphs;
+    void* scratch = nullptr;            // this device's copy of the no-allocation scratch array
+    unsigned long long* host_many = nullptr;  // pinned read-back area of tc_census_each_noalloc
     tc::batch_plan* batch = nullptr;    // cached batched launch (captured hipGraph), owned
     tc::serve_state* serve = nullptr;   // serving loop, started on first submit, owned
 };

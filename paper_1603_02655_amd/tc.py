@@ -30,6 +30,8 @@ TC_ERR_BUSY = -5
 TC_ERR_NOT_FOUND = -6
 TC_ERR_SHUTDOWN = -7
 
+TC_NOALLOC_MAX_GRAPHS = 256
+
 TC_BUILD_DEFAULT = 0
 TC_BUILD_STRICT = 1
 TC_BUILD_DEVICE_PTRS = 2
@@ -109,6 +111,7 @@ SIGNATURES = {
     "tc_census64": (ctypes.c_int, [_vp, _vp, _vp]),
     "tc_census_batch": (ctypes.c_int, [_vp, _vp, _i32, _vp]),
     "tc_census_each": (ctypes.c_int, [_vp, _vp, _i32, _vp]),
+    "tc_census_each_noalloc": (ctypes.c_int, [_vp, _vp, _i32, _vp]),
     "tc_submit": (ctypes.c_int, [_vp, _vp, _P(_u64)]),
     "tc_submit_arcs": (ctypes.c_int, [_vp, _i32, _i64, _vp, _vp, _u32, _P(_u64)]),
     "tc_poll": (ctypes.c_int, [_vp, _u64, _vp, _P(ctypes.c_int)]),
@@ -301,6 +304,9 @@ class Context:
 
     def census_each(self, graphs) -> np.ndarray:
         return self._many("tc_census_each", list(graphs))
+
+    def census_each_noalloc(self, graphs) -> np.ndarray:
+        return self._many("tc_census_each_noalloc", list(graphs))
 
     # -- serving ---------------------------------------------------------
     def submit(self, g: Graph) -> int:

@@ -110,6 +110,13 @@ typedef struct {
     uint32_t t_hub;
     uint32_t hub_blocks;     /* resident 256-thread blocks, hub kernel */
     uint32_t tri;            /* 1: whole-graph census through triangles of the forward lists */
+    /* LDS tiles and group size (each among the kernel variants the library is built with) */
+    uint32_t hub_tile;       /* anchor entries staged per LDS tile, hub mode: 512, 1024, 2048; graphs built
+                                or rebucketed while it is set group their hub tasks for it */
+    uint32_t wave_tile;      /* entries of each row staged per round, wave mode: 512, 1024, 2048 */
+    uint32_t group_tile;     /* entries of each row staged per round, group mode: 2048, 4096, 8192 */
+    uint32_t group_size;     /* threads per workgroup, group mode: 256, 512 */
+    uint32_t batch_tile;     /* wave-mode tile of the batched kernel (its group-mode tile is 4x): 512, 1024, 2048 */
 } tc_tuning;
 
 /* Accumulated device time of the census kernels, per bucket (lane, wave,

@@ -41,10 +41,27 @@ census_config config_of(const tc_tuning& t) {
     c.wave_blocks = t.wave_blocks;
     c.group_blocks = t.group_blocks;
     c.hub_blocks = t.hub_blocks;
+    c.hub_tile = t.hub_tile;
+    c.wave_tile = t.wave_tile;
+    c.group_tile = t.group_tile;
+    c.group_size = t.group_size;
     return c;
 }
 
-bucket_params params_of(const tc_tuning& t) { return bucket_params{t.t0, t.t1, t.t_hub, t.tri}; }
+bucket_params params_of(const tc_tuning& t) { return bucket_params{t.t0, t.t1, t.t_hub, t.tri, t.hub_tile}; }
+
+tc_tuning tuning_snapshot(tc_context_s* ctx) {
+    std::lock_guard<std::mutex> lk(ctx->tuning_mu);
+    return ctx->tuning;
+}
+
+int check_tuning(const tc_tuning& t) {
+    if (t.t0 > t.t1 || t.lane_blocks == 0 || t.wave_blocks == 0 || t.group_blocks == 0 || t.batch_blocks == 0 ||
+        t.hub_blocks == 0 || t.tri > 1)
+        return TC_ERR_ARG;
+    if (!tile_supported(t.hub_tile, t.wave_tile, t.group_tile, t.group_size, t.batch_tile)) return TC_ERR_ARG;
+    return TC_OK;
+}
 
 void fill_info(const tc_graph_s* g, tc_graph_info* info) {
     *info = g->info;
@@ -485,10 +502,9 @@ int tc_census_each_noalloc(tc_context ctx, const tc_graph* graphs, int32_t count
 
 int tc_set_tuning(tc_context ctx, const tc_tuning* t) {
     if (!ctx || !t) return TC_ERR_ARG;
-    if (t->t0 > t->t1 || t->lane_blocks == 0 || t->wave_blocks == 0 || t->group_blocks == 0 || t->batch_blocks == 0 ||
-        t->hub_blocks == 0 || t->tri > 1)
-        return TC_ERR_ARG;
+    if (check_tuning(*t) != TC_OK) return TC_ERR_ARG;
     std::lock_guard<std::mutex> lk(ctx->mu);
+    std::lock_guard<std::mutex> lt(ctx->tuning_mu);
     ctx->tuning = *t;
     return TC_OK;
 }
@@ -507,7 +523,8 @@ int tc_graph_rebucket(tc_context ctx, tc_graph g) {
     if (!ctx->graphs.count(g)) return TC_ERR_ARG;
     if (g->pending.load() > 0) return TC_ERR_BUSY;
     const bucket_params bp = params_of(ctx->tuning);
-    if (g->g.bp.t0 == bp.t0 && g->g.bp.t1 == bp.t1 && g->g.bp.t_hub == bp.t_hub && g->g.bp.tri == bp.tri)
+    if (g->g.bp.t0 == bp.t0 && g->g.bp.t1 == bp.t1 && g->g.bp.t_hub == bp.t_hub && g->g.bp.tri == bp.tri &&
+        g->g.bp.hub_tile == bp.hub_tile)
         return TC_OK;
     batch_forget_graph_locked(ctx, g);
     return status_from_hip(bucket_dyads(&g->g, bp, ctx->stream));

@@ -32,6 +32,8 @@ struct tc_context_s {
     int cu_count = 0;
     char arch[64] = {0};
     std::mutex mu;                      // serialises work on `stream` and the buffers below
+    std::mutex tuning_mu;               // held (inside mu) while `tuning` is written; lets the
+                                        // serving thread copy it without waiting for mu
     unsigned long long* acc = nullptr;  // 16 accumulators (device)
     unsigned int* counters = nullptr;   // work counters (device)
     unsigned long long* host_raw = nullptr;  // pinned copy of acc
@@ -70,6 +72,11 @@ int run_full_locked(tc_context_s* ctx, const device_graph& g, unsigned long long
 int build_into(int32_t n, int64_t m, const int32_t* src, const int32_t* dst, uint32_t flags, const bucket_params& bp,
                hipStream_t stream, device_graph* out, tc_graph_info* info);
 bucket_params params_of(const tc_tuning& t);
+// A copy of ctx->tuning taken under tuning_mu (for threads that do not hold mu).
+tc_tuning tuning_snapshot(tc_context_s* ctx);
+// TC_OK when every field of t is in range (thresholds ordered, grids non-zero,
+// tiles and group size among the built kernel variants).
+int check_tuning(const tc_tuning& t);
 
 inline tc_tuning default_tuning(int cu_count) {
     tc_tuning t;
@@ -83,6 +90,11 @@ inline tc_tuning default_tuning(int cu_count) {
     t.batch_blocks = (uint32_t)cu * 4;
     t.hub_blocks = (uint32_t)cu * 8;
     t.tri = 1;      // whole-graph census through the triangles of the forward lists
+    t.hub_tile = 1024;
+    t.wave_tile = 1024;
+    t.group_tile = 4096;
+    t.group_size = 256;
+    t.batch_tile = 512;
     return t;
 }
 

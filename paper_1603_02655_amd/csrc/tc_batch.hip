@@ -24,6 +24,7 @@ struct batch_plan {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     uint32_t grid = 0, hub_grid = 0;
+    uint32_t hub_tile = 0, batch_tile = 0;  // LDS tiles the captured kernels use
     bool valid = false;                     // buffers describe `graphs`
     bool tri = false;                       // ... through their forward lists
 
@@ -107,8 +108,9 @@ void append_items(const device_graph& g, uint32_t gi, bool tri, std::vector<work
 namespace {
 
 hipError_t ensure_capacity(batch_plan* p, uint32_t graphs, uint32_t items, hipStream_t s, uint32_t grid,
-                           uint32_t hub_grid) {
-    if (p->exec && graphs <= p->cap_graphs && items <= p->cap_items && grid == p->grid && hub_grid == p->hub_grid)
+                           uint32_t hub_grid, uint32_t hub_tile, uint32_t batch_tile) {
+    if (p->exec && graphs <= p->cap_graphs && items <= p->cap_items && grid == p->grid && hub_grid == p->hub_grid &&
+        hub_tile == p->hub_tile && batch_tile == p->batch_tile)
         return hipSuccess;
     (void)hipStreamSynchronize(s);
     p->release();
@@ -116,6 +118,8 @@ hipError_t ensure_capacity(batch_plan* p, uint32_t graphs, uint32_t items, hipSt
     p->cap_items = std::max<uint32_t>(items + items / 4, 1024);
     p->grid = grid;
     p->hub_grid = hub_grid;
+    p->hub_tile = hub_tile;
+    p->batch_tile = batch_tile;
     hipError_t e = hipMalloc((void**)&p->d_desc, sizeof(graph_desc) * p->cap_graphs);
     if (e == hipSuccess) e = hipMalloc((void**)&p->d_items, sizeof(work_item) * p->cap_items);
     if (e == hipSuccess) e = hipMalloc((void**)&p->d_num, 2 * sizeof(uint32_t));
@@ -131,7 +135,7 @@ hipError_t ensure_capacity(batch_plan* p, uint32_t graphs, uint32_t items, hipSt
     e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return e;
     hipError_t el = batch_launch(p->d_desc, p->d_items, p->d_num, p->d_accs, (uint64_t)kNumClasses * p->cap_graphs,
-                                 p->d_ctr, p->grid, p->hub_grid, s);
+                                 p->d_ctr, p->grid, p->hub_grid, p->hub_tile, p->batch_tile, s);
     hipError_t ec = hipMemcpyAsync(p->h_accs, p->d_accs, sizeof(unsigned long long) * kNumClasses * p->cap_graphs,
                                    hipMemcpyDeviceToHost, s);
     e = hipStreamEndCapture(s, &p->graph);
@@ -162,7 +166,8 @@ extern "C" int tc_census_batch(tc_context ctx, const tc_graph* graphs, int32_t c
     hipError_t e = hipSuccess;
     const bool tri = ctx->tuning.tri != 0;
     if (!(p->valid && p->graphs == want && p->grid == ctx->tuning.batch_blocks &&
-          p->hub_grid == ctx->tuning.hub_blocks && p->tri == tri)) {
+          p->hub_grid == ctx->tuning.hub_blocks && p->hub_tile == ctx->tuning.hub_tile &&
+          p->batch_tile == ctx->tuning.batch_tile && p->tri == tri)) {
         std::vector<work_item> items, rest;
         std::vector<graph_desc> descs(count);
         for (int32_t i = 0; i < count; ++i) {
@@ -173,7 +178,7 @@ extern "C" int tc_census_batch(tc_context ctx, const tc_graph* graphs, int32_t c
         const uint32_t nums[2] = {(uint32_t)items.size(), (uint32_t)(items.size() + rest.size())};
         items.insert(items.end(), rest.begin(), rest.end());     // hub items first
         e = ensure_capacity(p, (uint32_t)count, (uint32_t)items.size(), ctx->stream, ctx->tuning.batch_blocks,
-                            ctx->tuning.hub_blocks);
+                            ctx->tuning.hub_blocks, ctx->tuning.hub_tile, ctx->tuning.batch_tile);
         if (e != hipSuccess) return status_from_hip(e);
         uint32_t nitems = (uint32_t)items.size();
         e = hipMemcpyAsync(p->d_desc, descs.data(), sizeof(graph_desc) * count, hipMemcpyHostToDevice, ctx->stream);

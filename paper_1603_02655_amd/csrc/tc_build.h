@@ -53,7 +53,7 @@ struct device_graph {
     uint64_t bucket_cost[kBuckets] = {0, 0, 0, 0};   // sum of |N(u)|+|N(v)| per bucket
     uint64_t hub_stream = 0;   // sum over hub dyads of the non-anchor degree (entries probed)
     uint64_t hub_staged = 0;   // sum over hub tasks of the anchor degree (entries staged)
-    bucket_params bp{0, 0, 0, 0};
+    bucket_params bp{0, 0, 0, 0, kHubTileEntries};
     forward_lists tri;         // built when bp.tri
 };
 

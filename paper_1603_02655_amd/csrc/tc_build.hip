@@ -501,12 +501,12 @@ __global__ __launch_bounds__(kT) void k_hub_emit(const unsigned int* __restrict_
 // Groups of consecutive hub tasks that one workgroup runs with a single LDS
 // tile: each window of kHubGroupTasks tasks is cut greedily before a task whose
 // records would take the group past kHubChunk or whose anchor row would take
-// the group's rows past kHubTileEntries (a row longer than that stays alone).
+// the group's rows past `tile` entries (a row longer than that stays alone).
 // Without goff, counts the groups of every window into gcount; with goff (the
 // scanned counts), stores the first task of each group in tasks[g].group.
 __global__ __launch_bounds__(kT) void k_hub_group(hub_task* __restrict__ tasks, const dyad_rec* __restrict__ recs,
                                                   uint64_t ntasks, const uint64_t* __restrict__ goff,
-                                                  uint64_t* __restrict__ gcount) {
+                                                  uint64_t* __restrict__ gcount, uint32_t tile) {
     const uint64_t w = (uint64_t)blockIdx.x * kT + threadIdx.x;
     const uint64_t t0 = w * kHubGroupTasks;
     if (t0 >= ntasks) return;
@@ -517,7 +517,7 @@ __global__ __launch_bounds__(kT) void k_hub_group(hub_task* __restrict__ tasks, 
         const uint32_t b = tasks[t0 + j].begin, e = tasks[t0 + j].end, a = tasks[t0 + j].anchor;
         const dyad_rec r0 = recs[b];
         const uint32_t l = r0.u == a ? r0.eu - r0.bu : r0.ev - r0.bv, r = e - b;
-        if (j > gs && (l > kHubTileEntries || sr + r > kHubChunk || se + l > kHubTileEntries)) {
+        if (j > gs && (l > tile || sr + r > kHubChunk || se + l > tile)) {
             starts[ng++] = gs;
             gs = j;
             sr = 0;
@@ -755,7 +755,7 @@ static hipError_t bucket_records(const uint32_t* nbr, const uint32_t* owner, con
         uint64_t part[2] = {0, 0};
         for (int big = 1; big >= 0; --big) {
             hipLaunchKernelGGL(k_hub_ntasks, dim3(grid1((uint64_t)n)), dim3(kT), 0, s, hubcnt, n, row_ptr, tmp64,
-                               (uint64_t)kHubTileEntries, big, counters);
+                               (uint64_t)bp.hub_tile, big, counters);
             TRY(hipGetLastError());
             TRY(scan_exclusive_u64(tmp64, task_off, (uint64_t)n, task_off + n, s));
             TRY(hipMemcpyAsync(&part[big], task_off + n, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
@@ -765,11 +765,11 @@ static hipError_t bucket_records(const uint32_t* nbr, const uint32_t* owner, con
         TRY(hipMalloc((void**)&out->tasks, sizeof(hub_task) * (ntasks ? ntasks : 1)));
         for (int big = 1; big >= 0; --big) {
             hipLaunchKernelGGL(k_hub_ntasks, dim3(grid1((uint64_t)n)), dim3(kT), 0, s, hubcnt, n, row_ptr, tmp64,
-                               (uint64_t)kHubTileEntries, big, (unsigned long long*)nullptr);
+                               (uint64_t)bp.hub_tile, big, (unsigned long long*)nullptr);
             TRY(hipGetLastError());
             TRY(scan_exclusive_u64(tmp64, task_off, (uint64_t)n, task_off + n, s));
             hipLaunchKernelGGL(k_hub_emit, dim3(grid1((uint64_t)n)), dim3(kT), 0, s, hubcnt, n, row_ptr, rec_off,
-                               task_off, big ? (uint64_t)0 : part[1], (uint64_t)kHubTileEntries, big,
+                               task_off, big ? (uint64_t)0 : part[1], (uint64_t)bp.hub_tile, big,
                                out->off[kBucketHub], out->tasks);
             TRY(hipGetLastError());
         }
@@ -780,12 +780,13 @@ static hipError_t bucket_records(const uint32_t* nbr, const uint32_t* owner, con
         uint64_t ngroups = 0;
         TRY(hipMallocAsync((void**)&gcount, sizeof(uint64_t) * (windows + 1), s));
         hipLaunchKernelGGL(k_hub_group, dim3(grid1(windows)), dim3(kT), 0, s, out->tasks,
-                           (const dyad_rec*)out->recs, ntasks, (const uint64_t*)nullptr, gcount);
+                           (const dyad_rec*)out->recs, ntasks, (const uint64_t*)nullptr, gcount, bp.hub_tile);
         err = hipGetLastError();
         if (err == hipSuccess) err = scan_exclusive_u64(gcount, gcount, windows, gcount + windows, s);
         if (err == hipSuccess) {
             hipLaunchKernelGGL(k_hub_group, dim3(grid1(windows)), dim3(kT), 0, s, out->tasks,
-                               (const dyad_rec*)out->recs, ntasks, (const uint64_t*)gcount, (uint64_t*)nullptr);
+                               (const dyad_rec*)out->recs, ntasks, (const uint64_t*)gcount, (uint64_t*)nullptr,
+                               bp.hub_tile);
             err = hipGetLastError();
         }
         if (err == hipSuccess) err = hipMemcpyAsync(&ngroups, gcount + windows, sizeof(uint64_t), hipMemcpyDeviceToHost, s);

@@ -10,7 +10,15 @@ struct census_config {
     uint32_t group_blocks = 1024;   // resident workgroups of the group kernel
     uint32_t hub_blocks = 1024;     // resident workgroups of the hub kernel
     uint32_t side_blocks = 256;     // workgroups of the totals pass when it runs on the side stream
+    uint32_t hub_tile = 1024;       // anchor entries per LDS tile, hub mode (512, 1024, 2048)
+    uint32_t wave_tile = 1024;      // row entries staged per round, wave mode (512, 1024, 2048)
+    uint32_t group_tile = 4096;     // row entries staged per round, group mode (2048, 4096, 8192)
+    uint32_t group_size = 256;      // threads per workgroup, group mode (256, 512)
 };
+
+// Whether the kernels are built for these LDS tiles and group size.
+bool tile_supported(uint32_t hub_tile, uint32_t wave_tile, uint32_t group_tile, uint32_t group_size,
+                    uint32_t batch_tile);
 
 // Per-bucket dyad slices [begin, end) into g.dyads (merge buckets); the hub
 // bucket always runs all its tasks, restricted to dyads with u in [u_lo, u_hi).
@@ -50,12 +58,14 @@ constexpr uint32_t kBatchLanePerItem = 256;   // one dyad per thread of a 256-th
 constexpr uint32_t kBatchWavePerItem = 16;    // four wavefronts, four dyads each
 
 // Zeroes accs[0..acc_words) and 16 work counters, then runs two persistent
-// kernels: the hub kernel over the hub items items[0..nums[0]) with hub_grid
-// workgroups, and the batch kernel over the other items items[nums[0]..nums[1])
-// with `grid` workgroups (nums: 2 words of device memory).
+// kernels: the hub kernel (LDS tile of hub_tile anchor entries) over the hub
+// items items[0..nums[0]) with hub_grid workgroups, and the batch kernel
+// (wave-mode tile batch_tile, group-mode tile 4 x batch_tile) over the other
+// items items[nums[0]..nums[1]) with `grid` workgroups (nums: 2 words of
+// device memory).  hipErrorInvalidValue for a tile the kernels are not built for.
 hipError_t batch_launch(const graph_desc* descs, const work_item* items, const uint32_t* nums,
                         unsigned long long* accs, uint64_t acc_words, unsigned int* counters, uint32_t grid,
-                        uint32_t hub_grid, hipStream_t s);
+                        uint32_t hub_grid, uint32_t hub_tile, uint32_t batch_tile, hipStream_t s);
 
 // Copies the 16-class table into the constant table the batch kernel reads.
 hipError_t census_upload_table();

@@ -515,14 +515,14 @@ __device__ inline uint32_t take_chunk(unsigned int* ctr, uint32_t xcd) {
 
 // ---------------------------------------------------------------- wave ----
 constexpr int kWaveB = 64;
-constexpr int kWaveTile = 1024;
 constexpr uint32_t kWaveChunk = 16;
 
-template <bool Tri>
+// TW: entries of each row staged per round (the tunable LDS tile).
+template <bool Tri, int TW>
 __global__ __launch_bounds__(kWaveB) void k_census_wave(census_args L, unsigned int* ctr) {
     __shared__ unsigned long long bins[wave_bins<kWaveB>::kWords];
     __shared__ uint8_t T[64];
-    __shared__ uint32_t sA[kWaveTile + 1], sB[kWaveTile + 1];
+    __shared__ uint32_t sA[TW + 1], sB[TW + 1];
     __shared__ uint32_t s_xt;
     T[threadIdx.x] = L.table[threadIdx.x];
     wave_bins<kWaveB> h{bins};
@@ -540,7 +540,7 @@ __global__ __launch_bounds__(kWaveB) void k_census_wave(census_args L, unsigned 
             const dyad_rec r = load_rec(L.dyads + d);
             dyad_totals t{};
             if (!Tri && threadIdx.x == 0) t = load_totals(r, L.tpre);
-            merge_path<kWaveB, kWaveTile, block_sync, Tri>(r, L.nbr, sA, sB, &s_xt, threadIdx.x, T, h);
+            merge_path<kWaveB, TW, block_sync, Tri>(r, L.nbr, sA, sB, &s_xt, threadIdx.x, T, h);
             if (!Tri && threadIdx.x == 0) add_totals(r, t, L.n, T, h);
         }
         c = __shfl(cn, 0, 64);
@@ -549,18 +549,17 @@ __global__ __launch_bounds__(kWaveB) void k_census_wave(census_args L, unsigned 
 }
 
 // --------------------------------------------------------------- group ----
-constexpr int kGroupB = 256;
-constexpr int kGroupTile = 4096;
 constexpr uint32_t kGroupChunk = 2;
 
-template <bool Tri>
-__global__ __launch_bounds__(kGroupB) void k_census_group(census_args L, unsigned int* ctr) {
-    __shared__ unsigned long long bins[wave_bins<kGroupB>::kWords];
+// B: workgroup size; TW: entries of each row staged per round (both tunable).
+template <bool Tri, int B, int TW>
+__global__ __launch_bounds__(B) void k_census_group(census_args L, unsigned int* ctr) {
+    __shared__ unsigned long long bins[wave_bins<B>::kWords];
     __shared__ uint8_t T[64];
-    __shared__ uint32_t sA[kGroupTile + 1], sB[kGroupTile + 1];
+    __shared__ uint32_t sA[TW + 1], sB[TW + 1];
     __shared__ uint32_t s_xt, s_next;
     if (threadIdx.x < 64) T[threadIdx.x] = L.table[threadIdx.x];
-    wave_bins<kGroupB> h{bins};
+    wave_bins<B> h{bins};
     h.clear();
     const uint32_t xcd = blockIdx.x % kXcds;
     if (threadIdx.x == 0) s_next = take_chunk(ctr, xcd);
@@ -574,7 +573,7 @@ __global__ __launch_bounds__(kGroupB) void k_census_group(census_args L, unsigne
             const dyad_rec r = load_rec(L.dyads + d);
             dyad_totals t{};
             if (!Tri && threadIdx.x == 0) t = load_totals(r, L.tpre);
-            merge_path<kGroupB, kGroupTile, block_sync, Tri>(r, L.nbr, sA, sB, &s_xt, threadIdx.x, T, h);
+            merge_path<B, TW, block_sync, Tri>(r, L.nbr, sA, sB, &s_xt, threadIdx.x, T, h);
             if (!Tri && threadIdx.x == 0) add_totals(r, t, L.n, T, h);
         }
         __syncthreads();
@@ -596,11 +595,6 @@ __global__ __launch_bounds__(kGroupB) void k_census_group(census_args L, unsigne
 // vertex range holds it.  The anchor row is thus read once per task instead of
 // once per record, and the work per record is proportional to the shorter row.
 constexpr int kHubB = 256;
-constexpr uint32_t kHubTile = kHubTileEntries;
-constexpr uint32_t kHubBuckets = kHubTile / 2;           // buckets of 4 slots, mean load 2 entries
-constexpr uint32_t kHubSlots = 4 * kHubBuckets;
-constexpr int kHubBucketBits = __builtin_ctz(kHubBuckets);
-static_assert((kHubBuckets & (kHubBuckets - 1)) == 0, "power-of-two bucket count");
 constexpr uint32_t kEmpty = 0xffffffffu;                 // never an entry (w < 2^23)
 constexpr uint32_t kHubGather = 8;
 constexpr uint32_t kHubFlushAfter = (1u << 24) - 1u;      // kHubB times this stays below 2^32
@@ -614,30 +608,46 @@ __device__ inline uint32_t find_first_ge(const uint32_t* __restrict__ nbr, uint3
     return lo;
 }
 
-__device__ inline uint32_t hub_bucket(uint32_t w) { return (w * 0x9E3779B1u) >> (32 - kHubBucketBits); }
-
-// Bit of a vertex in the tile's filter (another multiplier than the buckets').
-constexpr uint32_t kHubFilterShift = 32 - 13;
-constexpr uint32_t kHubFilterMul = 0x85EBCA6Bu;
-__device__ inline uint32_t hub_filter_bit(uint32_t w) { return (w * kHubFilterMul) >> kHubFilterShift; }
+// Geometry of one LDS tile of TILE anchor entries (the tunable hub tile): a
+// hash table of TILE / 2 buckets of 4 slots (mean load 2 entries) and a filter
+// of 8 bits per staged entry.
+constexpr uint32_t kHubFilterMul = 0x85EBCA6Bu;          // filter hash (another multiplier than the buckets')
+template <uint32_t TILE>
+struct hub_geom {
+    static constexpr uint32_t kBuckets = TILE / 2;
+    static constexpr uint32_t kSlots = 4 * kBuckets;
+    static constexpr int kBucketBits = __builtin_ctz(kBuckets);
+    static constexpr int kFilterLog = __builtin_ctz(TILE) + 3;
+    static constexpr uint32_t kFilterShift = 32 - kFilterLog;
+    static constexpr uint32_t kFilterBits = 1u << kFilterLog;
+    static_assert((TILE & (TILE - 1)) == 0 && TILE >= 256 && TILE <= 4096, "power-of-two tile");
+    static_assert(kFilterBits / 32 >= (uint32_t)kHubB / 8, "filter words");
+    __device__ static inline uint32_t bucket(uint32_t w) { return (w * 0x9E3779B1u) >> (32 - kBucketBits); }
+    // bit of a vertex in the tile's filter
+    __device__ static inline uint32_t filter_bit(uint32_t w) { return (w * kHubFilterMul) >> kFilterShift; }
+};
 
 // Buckets fill their slots in order, so a bucket whose last slot is empty
 // ends the probe sequence of every vertex that hashes to it or before it.
+template <uint32_t TILE>
 __device__ inline void hub_insert(uint32_t* hash, uint32_t e) {
-    uint32_t b = hub_bucket(e >> 2);
+    using G = hub_geom<TILE>;
+    uint32_t b = G::bucket(e >> 2);
     for (;;) {
         for (uint32_t s = 0; s < 4; ++s)
             if (atomicCAS(&hash[4 * b + s], kEmpty, e) == kEmpty) return;
-        b = (b + 1) & (kHubBuckets - 1);
+        b = (b + 1) & (G::kBuckets - 1);
     }
 }
 
 // The whole bucket is read at once and its four slots compared without
 // branches (a vertex is stored at most once); the next bucket is read only
 // when this one is full and holds no match.
+template <uint32_t TILE>
 __device__ inline uint32_t hub_probe(const uint32_t* hash, uint32_t w) {
+    using G = hub_geom<TILE>;
     const uint4* h4 = reinterpret_cast<const uint4*>(hash);
-    uint32_t b = hub_bucket(w);
+    uint32_t b = G::bucket(w);
     for (;;) {
         const uint4 q = h4[b];
         uint32_t r = kEmpty;
@@ -646,7 +656,7 @@ __device__ inline uint32_t hub_probe(const uint32_t* hash, uint32_t w) {
         r = (q.z >> 2) == w ? q.z : r;
         r = (q.w >> 2) == w ? q.w : r;
         if (r != kEmpty || q.w == kEmpty) return r;
-        b = (b + 1) & (kHubBuckets - 1);
+        b = (b + 1) & (G::kBuckets - 1);
     }
 }
 
@@ -719,7 +729,7 @@ __device__ inline uint32_t hub_blocks(uint32_t p0, uint32_t p1) {
 // task words.
 constexpr uint32_t kHubRing = 128;   // candidates a wavefront holds between probe rounds
 struct hub_lds {
-    uint32_t* hash;   // kHubSlots, 16-byte aligned
+    uint32_t* hash;   // hub_geom::kSlots, 16-byte aligned
     uint2* ring;      // kHubRing x (kHubB / 64) candidates: (entry, meta word of its record)
     uint32_t* pos;    // next unprobed position in the other endpoint's row
     uint32_t* end;    // end of that row's entries in the current tile
@@ -727,23 +737,35 @@ struct hub_lds {
     uint32_t* off;    // blocks of this tile, then their exclusive scan and kScanPad copies of the total
     uint32_t* wsum;   // 4 words
     uint32_t* sig;    // kSigs counts shared by the workgroup
-    uint32_t* filt;   // kHubFilterBits bits: a vertex whose bit is clear is not in the tile
+    uint32_t* filt;   // hub_geom::kFilterBits bits: a vertex whose bit is clear is not in the tile
     uint32_t* tk;     // kHubTkWords: the tasks of the current chunk and their groups
 };
-constexpr uint32_t kHubFilterBits = 1u << (32 - kHubFilterShift);
 // Words of hub_lds::tk: per task of the chunk its first record, record count,
 // anchor-row start, anchor-row length and anchor; the group boundaries and
 // their count; the record and row prefixes of the current group's members.
 constexpr uint32_t kTkBegin = 0, kTkNrec = 8, kTkHb = 16, kTkLen = 24, kTkAnchor = 32, kTkGroups = 40,
                    kTkNGroups = 49, kTkRb = 50, kTkEb = 59, kHubTkWords = 68;
 static_assert(kHubGroupTasks == 8, "the task words hold eight tasks");
-constexpr uint32_t kHubLdsWords = kHubSlots + 2 * kHubRing * (kHubB / 64) + 3 * kHubChunk + (kHubChunk + kScanPad) + 4 +
-                                  kSigs + kHubFilterBits / 32 + kHubTkWords;
+template <uint32_t TILE>
+constexpr uint32_t hub_lds_words() {
+    return hub_geom<TILE>::kSlots + 2 * kHubRing * (kHubB / 64) + 3 * kHubChunk + (kHubChunk + kScanPad) + 4 + kSigs +
+           hub_geom<TILE>::kFilterBits / 32 + kHubTkWords;
+}
 
+// Wavefronts per SIMD the hub kernels are compiled for: seven (the best
+// measured with 1024-entry tiles), or as many workgroups as the LDS of a CU
+// (160 KiB) holds for larger tiles.
+template <uint32_t TILE>
+constexpr uint32_t hub_waves_per_simd() {
+    return (163840u / (4u * hub_lds_words<TILE>() + 1024u)) < 7u ? (163840u / (4u * hub_lds_words<TILE>() + 1024u))
+                                                                 : 7u;
+}
+
+template <uint32_t TILE>
 __device__ inline hub_lds hub_carve(uint32_t* base) {
     uint32_t* p = base;
     hub_lds S;
-    S.hash = p;  p += kHubSlots;
+    S.hash = p;  p += hub_geom<TILE>::kSlots;
     S.ring = reinterpret_cast<uint2*>(p);  p += 2 * kHubRing * (kHubB / 64);
     S.pos = p;   p += kHubChunk;
     S.end = p;   p += kHubChunk;
@@ -751,7 +773,7 @@ __device__ inline hub_lds hub_carve(uint32_t* base) {
     S.off = p;   p += kHubChunk + kScanPad;
     S.wsum = p;  p += 4;
     S.sig = p;   p += kSigs;
-    S.filt = p;  p += kHubFilterBits / 32;
+    S.filt = p;  p += hub_geom<TILE>::kFilterBits / 32;
     S.tk = p;
     return S;
 }
@@ -787,16 +809,17 @@ __device__ inline void hub_bins_flush(const hub_lds& S, const uint8_t* T, H& h) 
 // then each wavefront walks a quarter of the flattened block list, one block
 // per lane, and probes the entries that pass the tile's filter 64 at a time.
 // A hit adds one to the workgroup's count of the hit's signature.
-template <bool Tri, class H>
+template <bool Tri, uint32_t TILE, class H>
 __device__ inline void hub_group_run(uint32_t js, uint32_t M, const dyad_rec* __restrict__ dyads,
                                      const uint32_t* __restrict__ nbr, const uint64_t* __restrict__ tpre, uint64_t n,
                                      uint32_t u_lo, uint32_t u_hi, const hub_lds& S, const uint8_t* T, H& h,
                                      uint32_t& since) {
+    using G = hub_geom<TILE>;
     const uint32_t tid = threadIdx.x;
     const uint32_t* rb = S.tk + kTkRb;   // record prefix of the members (M + 1 words)
     const uint32_t* eb = S.tk + kTkEb;   // anchor-row prefix of the members (M + 1 words)
     const uint32_t nrec = rb[M], total = eb[M];
-    const bool multi_tile = total > kHubTile;   // a single task
+    const bool multi_tile = total > TILE;   // a single task
     for (uint32_t i = tid; i < nrec; i += kHubB) {
         uint32_t m = 0;
         while (m + 1 < M && rb[m + 1] <= i) ++m;
@@ -815,17 +838,17 @@ __device__ inline void hub_group_run(uint32_t js, uint32_t M, const dyad_rec* __
         }
         if (!Tri && in) add_totals(r, load_totals(r, tpre), n, T, h);
     }
-    for (uint32_t tb = 0; tb < total; tb += kHubTile) {
-        const uint32_t te = min(total, tb + kHubTile);
-        for (uint32_t k = tid; k < kHubSlots; k += kHubB) S.hash[k] = kEmpty;
-        for (uint32_t k = tid; k < kHubFilterBits / 32; k += kHubB) S.filt[k] = 0;
+    for (uint32_t tb = 0; tb < total; tb += TILE) {
+        const uint32_t te = min(total, tb + TILE);
+        for (uint32_t k = tid; k < G::kSlots; k += kHubB) S.hash[k] = kEmpty;
+        for (uint32_t k = tid; k < G::kFilterBits / 32; k += kHubB) S.filt[k] = 0;
         __syncthreads();
         for (uint32_t f = tb + tid; f < te; f += kHubB) {
             uint32_t m = 0;
             while (m + 1 < M && eb[m + 1] <= f) ++m;
             const uint32_t v = nbr[S.tk[kTkHb + js + m] + (f - eb[m])];
-            hub_insert(S.hash, (m << 25) | v);
-            const uint32_t fb = hub_filter_bit((m << 23) | (v >> 2));
+            hub_insert<TILE>(S.hash, (m << 25) | v);
+            const uint32_t fb = G::filter_bit((m << 23) | (v >> 2));
             atomicOr(&S.filt[fb >> 5], 1u << (fb & 31u));
         }
         if (multi_tile) {
@@ -875,7 +898,7 @@ __device__ inline void hub_group_run(uint32_t js, uint32_t M, const dyad_rec* __
             if (lane < c) {
                 const uint2 q = ring[lane];
                 const uint32_t w = q.x >> 2, m = q.y >> 26;
-                const uint32_t hit = hub_probe(S.hash, (m << 23) | w);
+                const uint32_t hit = hub_probe<TILE>(S.hash, (m << 23) | w);
                 if (hit != kEmpty) {
                     const uint32_t a = S.tk[kTkAnchor + js + m];
                     const uint32_t x = (q.y >> 3) & ((1u << 23) - 1u), fuv = q.y & 3u;
@@ -936,16 +959,16 @@ __device__ inline void hub_group_run(uint32_t js, uint32_t M, const dyad_rec* __
                     vm = ((1u << khi) - 1u) & ~((1u << klo) - 1u);
                 }
                 // Filter: the word of every entry first, then the bits.  The
-                // filter of a key k has bit (k * C) >> kHubFilterShift set.
+                // filter of a key k has bit (k * C) >> kFilterShift set.
                 const uint32_t mkey = (m >> 26) << 23;
                 uint32_t hk[kHubGather], fw[kHubGather], pm = 0;
 #pragma unroll
                 for (uint32_t k = 0; k < kHubGather; ++k) {
                     hk[k] = (mkey | (e[k] >> 2)) * kHubFilterMul;
-                    fw[k] = S.filt[hk[k] >> (kHubFilterShift + 5)];
+                    fw[k] = S.filt[hk[k] >> (G::kFilterShift + 5)];
                 }
 #pragma unroll
-                for (uint32_t k = 0; k < kHubGather; ++k) pm |= ((fw[k] >> ((hk[k] >> kHubFilterShift) & 31u)) & 1u) << k;
+                for (uint32_t k = 0; k < kHubGather; ++k) pm |= ((fw[k] >> ((hk[k] >> G::kFilterShift) & 31u)) & 1u) << k;
                 pm &= vm;
                 // appends: the entries that pass go to ring[cnt ..] in lane order
 #pragma unroll
@@ -982,7 +1005,7 @@ __device__ inline void hub_group_run(uint32_t js, uint32_t M, const dyad_rec* __
 // descriptors and anchor rows are read once, and runs of consecutive tasks
 // whose records fit one chunk and whose anchor rows fit one tile are
 // processed together; a task whose anchor row spans several tiles runs alone.
-template <bool Tri, class H>
+template <bool Tri, uint32_t TILE, class H>
 __device__ inline void hub_chunk_run(const hub_task* __restrict__ tasks, uint32_t t0, uint32_t t1,
                                      const dyad_rec* __restrict__ dyads, const uint32_t* __restrict__ nbr,
                                      const uint64_t* __restrict__ tpre, uint64_t n, uint32_t u_lo, uint32_t u_hi,
@@ -1005,7 +1028,7 @@ __device__ inline void hub_chunk_run(const hub_task* __restrict__ tasks, uint32_
         S.tk[kTkGroups] = 0;
         for (uint32_t j = 0; j < nt; ++j) {
             const uint32_t r = S.tk[kTkNrec + j], l = S.tk[kTkLen + j];
-            if (j > S.tk[kTkGroups + ng] && (l > kHubTile || sr + r > kHubChunk || se + l > kHubTile)) {
+            if (j > S.tk[kTkGroups + ng] && (l > TILE || sr + r > kHubChunk || se + l > TILE)) {
                 S.tk[kTkGroups + ++ng] = j;
                 sr = 0;
                 se = 0;
@@ -1032,22 +1055,23 @@ __device__ inline void hub_chunk_run(const hub_task* __restrict__ tasks, uint32_
             S.tk[kTkEb + M] = e;
         }
         __syncthreads();
-        hub_group_run<Tri>(js, M, dyads, nbr, tpre, n, u_lo, u_hi, S, T, h, since);
+        hub_group_run<Tri, TILE>(js, M, dyads, nbr, tpre, n, u_lo, u_hi, S, T, h, since);
         __syncthreads();
     }
 }
 
-template <bool Tri>
-__global__ __launch_bounds__(kHubB) __attribute__((amdgpu_waves_per_eu(7, 7))) void k_census_hub(census_args L, const hub_task* __restrict__ tasks,
-                                                      uint32_t ntasks, uint32_t ngroups, unsigned int* ctr) {
-    __shared__ __attribute__((aligned(16))) uint32_t hub_words[kHubLdsWords];
+template <bool Tri, uint32_t TILE>
+__global__ __launch_bounds__(kHubB)
+__attribute__((amdgpu_waves_per_eu(hub_waves_per_simd<TILE>(), hub_waves_per_simd<TILE>()))) void k_census_hub(
+    census_args L, const hub_task* __restrict__ tasks, uint32_t ntasks, uint32_t ngroups, unsigned int* ctr) {
+    __shared__ __attribute__((aligned(16))) uint32_t hub_words[hub_lds_words<TILE>()];
     __shared__ unsigned long long bins[block_bins<kHubB>::kWords];
     __shared__ uint8_t T[64];
     __shared__ uint32_t s_next;
     if (threadIdx.x < 64) T[threadIdx.x] = L.table[threadIdx.x];
     block_bins<kHubB> h{bins};
     h.clear();
-    const hub_lds S = hub_carve(hub_words);
+    const hub_lds S = hub_carve<TILE>(hub_words);
     hub_bins_clear(S);
     __syncthreads();
     uint32_t since = 0;
@@ -1059,7 +1083,7 @@ __global__ __launch_bounds__(kHubB) __attribute__((amdgpu_waves_per_eu(7, 7))) v
     while (c < ngroups) {
         if (threadIdx.x == 0) s_next = take_chunk(ctr, xcd);
         const uint32_t t0 = tasks[c].group, t1 = c + 1 < ngroups ? tasks[c + 1].group : ntasks;
-        hub_chunk_run<Tri>(tasks, t0, t1, L.dyads, L.nbr, L.tpre, L.n, L.u_lo, L.u_hi, S, T, h, since);
+        hub_chunk_run<Tri, TILE>(tasks, t0, t1, L.dyads, L.nbr, L.tpre, L.n, L.u_lo, L.u_hi, S, T, h, since);
         c = s_next;
         __syncthreads();
     }
@@ -1079,16 +1103,17 @@ __global__ __launch_bounds__(kHubB) __attribute__((amdgpu_waves_per_eu(7, 7))) v
 // to per-wavefront bins that are flushed into the graph's 16 accumulators
 // whenever the workgroup moves to another graph.
 constexpr int kBatchB = 256;
-constexpr int kBatchWaveTile = 512;
-constexpr int kBatchGroupTile = 2048;
-constexpr int kBatchMergeWords = (4 * 2 * (kBatchWaveTile + 1) > 2 * (kBatchGroupTile + 1))
-                                     ? 4 * 2 * (kBatchWaveTile + 1) : 2 * (kBatchGroupTile + 1);
-constexpr int kBatchTileWords = kBatchMergeWords;
+// The tile area of k_census_batch for wave-mode tile TW (the tunable batch
+// tile; the group-mode tile is 4 TW): four wavefronts' pairs of TW-entry
+// tiles, or one pair of 4 TW-entry tiles.
+template <int TW>
+constexpr int batch_tile_words() {
+    return (4 * 2 * (TW + 1) > 2 * (4 * TW + 1)) ? 4 * 2 * (TW + 1) : 2 * (4 * TW + 1);
+}
 static_assert(kBatchTotalsPerItem % kBatchB == 0, "totals items are whole steps of the workgroup");
 static_assert(kBatchB == kLaneB, "the slot helpers assume 256-lane workgroups");
-static_assert(2 * kTotalsSlots * kBatchB <= kBatchTileWords, "per-lane slots fit in the tile area");
 
-template <bool Tri, class H>
+template <bool Tri, int TW, class H>
 __device__ inline void batch_item(uint32_t kind, const work_item& it, const graph_desc& g, uint32_t* tiles,
                                   uint32_t* s_xt, const uint8_t* T, H& h) {
     const uint32_t tid = threadIdx.x, wid = tid >> 6, lane = tid & 63u;
@@ -1098,36 +1123,37 @@ __device__ inline void batch_item(uint32_t kind, const work_item& it, const grap
         const uint32_t d = it.begin + tid;
         if (d < it.end) lane_dyad<Tri>(load_rec(recs + d), nbr, g.tpre, g.n, T, h);
     } else if (kind == kItemWave) {
-        uint32_t* sA = tiles + wid * 2 * (kBatchWaveTile + 1);
-        uint32_t* sB = sA + kBatchWaveTile + 1;
+        uint32_t* sA = tiles + wid * 2 * (TW + 1);
+        uint32_t* sB = sA + TW + 1;
         for (uint32_t d = it.begin + wid; d < it.end; d += kBatchB / 64) {
             const dyad_rec r = load_rec(recs + d);
             dyad_totals t{};
             if (!Tri && lane == 0) t = load_totals(r, g.tpre);
-            merge_path<64, kBatchWaveTile, wave_sync, Tri>(r, nbr, sA, sB, &s_xt[wid], lane, T, h);
+            merge_path<64, TW, wave_sync, Tri>(r, nbr, sA, sB, &s_xt[wid], lane, T, h);
             if (!Tri && lane == 0) add_totals(r, t, g.n, T, h);
         }
     } else if (kind == kItemGroup) {
         const dyad_rec r = load_rec(recs + it.begin);
         dyad_totals t{};
         if (!Tri && tid == 0) t = load_totals(r, g.tpre);
-        merge_path<kBatchB, kBatchGroupTile, block_sync, Tri>(r, nbr, tiles, tiles + kBatchGroupTile + 1, &s_xt[0],
-                                                              tid, T, h);
+        merge_path<kBatchB, 4 * TW, block_sync, Tri>(r, nbr, tiles, tiles + 4 * TW + 1, &s_xt[0], tid, T, h);
         if (!Tri && tid == 0) add_totals(r, t, g.n, T, h);
     }
 }
 
-__global__ __launch_bounds__(kHubB) __attribute__((amdgpu_waves_per_eu(7, 7))) void k_census_batch_hub(
+template <uint32_t TILE>
+__global__ __launch_bounds__(kHubB)
+__attribute__((amdgpu_waves_per_eu(hub_waves_per_simd<TILE>(), hub_waves_per_simd<TILE>()))) void k_census_batch_hub(
     const graph_desc* __restrict__ G, const work_item* __restrict__ items, const uint32_t* __restrict__ nums,
     unsigned long long* __restrict__ accs, unsigned int* __restrict__ ctr) {
-    __shared__ __attribute__((aligned(16))) uint32_t hub_words[kHubLdsWords];
+    __shared__ __attribute__((aligned(16))) uint32_t hub_words[hub_lds_words<TILE>()];
     __shared__ unsigned long long bins[block_bins<kHubB>::kWords];
     __shared__ uint8_t T[64];
     __shared__ uint32_t s_next;
     if (threadIdx.x < 64) T[threadIdx.x] = c_table[threadIdx.x];
     block_bins<kHubB> h{bins};
     h.clear();
-    const hub_lds S = hub_carve(hub_words);
+    const hub_lds S = hub_carve<TILE>(hub_words);
     hub_bins_clear(S);
     __syncthreads();
     const uint32_t count = nums[0];
@@ -1159,11 +1185,13 @@ __global__ __launch_bounds__(kHubB) __attribute__((amdgpu_waves_per_eu(7, 7))) v
             if (cur_tri) {
                 const uint32_t t0 = g.edge_tasks[k].group;
                 const uint32_t t1 = k + 1 < g.tri_groups ? g.edge_tasks[k + 1].group : g.tri_tasks;
-                hub_chunk_run<true>(g.edge_tasks, t0, t1, g.edges, g.fwd, g.tpre, g.n, 0u, 0xffffffffu, S, T, h, since);
+                hub_chunk_run<true, TILE>(g.edge_tasks, t0, t1, g.edges, g.fwd, g.tpre, g.n, 0u, 0xffffffffu, S, T, h,
+                                          since);
             } else {
                 const uint32_t t0 = g.hub_tasks[k].group;
                 const uint32_t t1 = k + 1 < g.hub_groups ? g.hub_tasks[k + 1].group : g.hub_ntasks;
-                hub_chunk_run<false>(g.hub_tasks, t0, t1, g.dyads, g.nbr, g.tpre, g.n, 0u, 0xffffffffu, S, T, h, since);
+                hub_chunk_run<false, TILE>(g.hub_tasks, t0, t1, g.dyads, g.nbr, g.tpre, g.n, 0u, 0xffffffffu, S, T, h,
+                                           since);
             }
         }
         idx = s_next;
@@ -1176,12 +1204,14 @@ __global__ __launch_bounds__(kHubB) __attribute__((amdgpu_waves_per_eu(7, 7))) v
     }
 }
 
+template <int TW>
 __global__ __launch_bounds__(kBatchB) void k_census_batch(const graph_desc* __restrict__ G,
                                                           const work_item* __restrict__ items,
                                                           const uint32_t* __restrict__ num_items,
                                                           unsigned long long* __restrict__ accs,
                                                           unsigned int* __restrict__ ctr) {
-    __shared__ __attribute__((aligned(16))) uint32_t tiles[kBatchTileWords];
+    static_assert(2 * kTotalsSlots * kBatchB <= batch_tile_words<TW>(), "per-lane slots fit in the tile area");
+    __shared__ __attribute__((aligned(16))) uint32_t tiles[batch_tile_words<TW>()];
     __shared__ unsigned long long bins[wave_bins<kBatchB>::kWords];
     __shared__ uint8_t T[64], TS[64];
     __shared__ uint32_t s_xt[kBatchB / 64], s_next, bin_of_slot[kTotalsSlots], s_nslots;
@@ -1230,9 +1260,9 @@ __global__ __launch_bounds__(kBatchB) void k_census_batch(const graph_desc* __re
             }
         }
         else if (it.kind & kItemTri)
-            batch_item<true>(it.kind & 3u, it, g, tiles, s_xt, T, h);
+            batch_item<true, TW>(it.kind & 3u, it, g, tiles, s_xt, T, h);
         else
-            batch_item<false>(it.kind, it, g, tiles, s_xt, T, h);
+            batch_item<false, TW>(it.kind, it, g, tiles, s_xt, T, h);
         __syncthreads();
         idx = s_next;
         __syncthreads();
@@ -1255,14 +1285,49 @@ __global__ void k_zero_u64(unsigned long long* p, int n) {
 
 }  // namespace
 
+bool tile_supported(uint32_t hub_tile, uint32_t wave_tile, uint32_t group_tile, uint32_t group_size,
+                    uint32_t batch_tile) {
+    const bool hub = hub_tile == 512 || hub_tile == 1024 || hub_tile == 2048;
+    const bool wave = wave_tile == 512 || wave_tile == 1024 || wave_tile == 2048;
+    const bool group = group_tile == 2048 || group_tile == 4096 || group_tile == 8192;
+    const bool gsize = group_size == 256 || group_size == 512;
+    const bool batch = batch_tile == 512 || batch_tile == 1024 || batch_tile == 2048;
+    return hub && wave && group && gsize && batch;
+}
+
+namespace {
+
+template <uint32_t HT, int BT>
+void launch_batch_kernels(const graph_desc* descs, const work_item* items, const uint32_t* nums,
+                          unsigned long long* accs, unsigned int* counters, uint32_t grid, uint32_t hub_grid,
+                          hipStream_t s) {
+    hipLaunchKernelGGL(k_census_batch_hub<HT>, dim3(hub_grid), dim3(kHubB), 0, s, descs, items, nums, accs,
+                       counters);
+    hipLaunchKernelGGL(k_census_batch<BT>, dim3(grid), dim3(kBatchB), 0, s, descs, items, nums, accs,
+                       counters + kXcds);
+}
+
+template <uint32_t HT>
+void launch_batch_bt(uint32_t bt, const graph_desc* descs, const work_item* items, const uint32_t* nums,
+                     unsigned long long* accs, unsigned int* counters, uint32_t grid, uint32_t hub_grid,
+                     hipStream_t s) {
+    if (bt == 512) launch_batch_kernels<HT, 512>(descs, items, nums, accs, counters, grid, hub_grid, s);
+    else if (bt == 1024) launch_batch_kernels<HT, 1024>(descs, items, nums, accs, counters, grid, hub_grid, s);
+    else launch_batch_kernels<HT, 2048>(descs, items, nums, accs, counters, grid, hub_grid, s);
+}
+
+}  // namespace
+
 hipError_t batch_launch(const graph_desc* descs, const work_item* items, const uint32_t* nums,
                         unsigned long long* accs, uint64_t acc_words, unsigned int* counters, uint32_t grid,
-                        uint32_t hub_grid, hipStream_t s) {
+                        uint32_t hub_grid, uint32_t hub_tile, uint32_t batch_tile, hipStream_t s) {
+    if (!tile_supported(hub_tile, 1024, 4096, 256, batch_tile)) return hipErrorInvalidValue;
     uint32_t zb = (uint32_t)std::min<uint64_t>((acc_words + 255) / 256, 1024);
     hipLaunchKernelGGL(k_fill_u64_grid, dim3(zb ? zb : 1), dim3(256), 0, s, accs, acc_words);
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, counters, 2 * kXcds);
-    hipLaunchKernelGGL(k_census_batch_hub, dim3(hub_grid), dim3(kHubB), 0, s, descs, items, nums, accs, counters);
-    hipLaunchKernelGGL(k_census_batch, dim3(grid), dim3(kBatchB), 0, s, descs, items, nums, accs, counters + kXcds);
+    if (hub_tile == 512) launch_batch_bt<512>(batch_tile, descs, items, nums, accs, counters, grid, hub_grid, s);
+    else if (hub_tile == 1024) launch_batch_bt<1024>(batch_tile, descs, items, nums, accs, counters, grid, hub_grid, s);
+    else launch_batch_bt<2048>(batch_tile, descs, items, nums, accs, counters, grid, hub_grid, s);
     return hipGetLastError();
 }
 
@@ -1280,20 +1345,37 @@ void launch_bucket(int b, const census_args& L, uint64_t cnt, const census_confi
         size_t sh = Tri ? 0 : sizeof(unsigned long long) * lane_bins<kLaneB>::kWords;
         hipLaunchKernelGGL(k_census_lane<Tri>, dim3(grid), dim3(kLaneB), sh, s, L);
     } else if (b == 1) {
-        uint32_t grid = (uint32_t)std::min<uint64_t>(cnt, cfg.wave_blocks);
-        hipLaunchKernelGGL(k_census_wave<Tri>, dim3(grid), dim3(kWaveB), 0, s, L, counters + kXcds);
+        const dim3 grid((uint32_t)std::min<uint64_t>(cnt, cfg.wave_blocks));
+        unsigned int* c = counters + kXcds;
+        if (cfg.wave_tile == 512) hipLaunchKernelGGL((k_census_wave<Tri, 512>), grid, dim3(kWaveB), 0, s, L, c);
+        else if (cfg.wave_tile == 1024) hipLaunchKernelGGL((k_census_wave<Tri, 1024>), grid, dim3(kWaveB), 0, s, L, c);
+        else hipLaunchKernelGGL((k_census_wave<Tri, 2048>), grid, dim3(kWaveB), 0, s, L, c);
     } else if (b == 2) {
-        uint32_t grid = (uint32_t)std::min<uint64_t>(cnt, cfg.group_blocks);
-        hipLaunchKernelGGL(k_census_group<Tri>, dim3(grid), dim3(kGroupB), 0, s, L, counters + 2 * kXcds);
+        const dim3 grid((uint32_t)std::min<uint64_t>(cnt, cfg.group_blocks));
+        unsigned int* c = counters + 2 * kXcds;
+        if (cfg.group_size == 256) {
+            if (cfg.group_tile == 2048) hipLaunchKernelGGL((k_census_group<Tri, 256, 2048>), grid, dim3(256), 0, s, L, c);
+            else if (cfg.group_tile == 4096) hipLaunchKernelGGL((k_census_group<Tri, 256, 4096>), grid, dim3(256), 0, s, L, c);
+            else hipLaunchKernelGGL((k_census_group<Tri, 256, 8192>), grid, dim3(256), 0, s, L, c);
+        } else {
+            if (cfg.group_tile == 2048) hipLaunchKernelGGL((k_census_group<Tri, 512, 2048>), grid, dim3(512), 0, s, L, c);
+            else if (cfg.group_tile == 4096) hipLaunchKernelGGL((k_census_group<Tri, 512, 4096>), grid, dim3(512), 0, s, L, c);
+            else hipLaunchKernelGGL((k_census_group<Tri, 512, 8192>), grid, dim3(512), 0, s, L, c);
+        }
     }
 }
 
 template <bool Tri>
 void launch_hub(const census_args& L, const hub_task* tasks, uint32_t ntasks, uint32_t ngroups,
                 const census_config& cfg, unsigned int* counters, hipStream_t s) {
-    uint32_t grid = (uint32_t)std::min<uint64_t>(ngroups, cfg.hub_blocks);
-    hipLaunchKernelGGL(k_census_hub<Tri>, dim3(grid), dim3(kHubB), 0, s, L, tasks, ntasks, ngroups,
-                       counters + 3 * kXcds);
+    const dim3 grid((uint32_t)std::min<uint64_t>(ngroups, cfg.hub_blocks));
+    unsigned int* c = counters + 3 * kXcds;
+    if (cfg.hub_tile == 512)
+        hipLaunchKernelGGL((k_census_hub<Tri, 512>), grid, dim3(kHubB), 0, s, L, tasks, ntasks, ngroups, c);
+    else if (cfg.hub_tile == 1024)
+        hipLaunchKernelGGL((k_census_hub<Tri, 1024>), grid, dim3(kHubB), 0, s, L, tasks, ntasks, ngroups, c);
+    else
+        hipLaunchKernelGGL((k_census_hub<Tri, 2048>), grid, dim3(kHubB), 0, s, L, tasks, ntasks, ngroups, c);
 }
 
 }  // namespace
@@ -1301,6 +1383,8 @@ void launch_hub(const census_args& L, const hub_task* tasks, uint32_t ntasks, ui
 hipError_t census_launch(const device_graph& g, const census_slices& sl, bool tri, const uint8_t* table,
                          unsigned long long* acc, unsigned int* counters, const census_config& cfg, hipStream_t s,
                          hipEvent_t* ev, hipStream_t side, hipEvent_t* fork) {
+    if (!tile_supported(cfg.hub_tile, cfg.wave_tile, cfg.group_tile, cfg.group_size, 1024))
+        return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, acc, kNumClasses);
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, counters, kBuckets * kXcds);
     const dyad_rec* recs = tri ? g.tri.edges.recs : g.dyads;

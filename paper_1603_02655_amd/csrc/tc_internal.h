@@ -43,7 +43,7 @@ struct hub_task {
     uint32_t begin, end, anchor, group;
 };
 constexpr uint32_t kHubChunk = 512;           // records per hub task
-constexpr uint32_t kHubTileEntries = 1024;    // anchor-row entries staged per LDS tile
+constexpr uint32_t kHubTileEntries = 1024;    // anchor-row entries staged per LDS tile (default)
 constexpr uint32_t kHubGroupTasks = 8;        // consecutive hub tasks a workgroup takes at a time
 constexpr uint64_t kRowPad = 8;               // entries allocated past the end of a row array (block reads)
 
@@ -52,7 +52,8 @@ constexpr uint64_t kRowPad = 8;               // entries allocated past the end 
 // others by k = |N(u)| + |N(v)| - 2: lane if k < t0, wave if k < t1, else group.
 struct bucket_params {
     uint32_t t0, t1, t_hub;
-    uint32_t tri;   // also build the degree-ordered forward lists and their edge records
+    uint32_t tri;        // also build the degree-ordered forward lists and their edge records
+    uint32_t hub_tile;   // anchor entries per LDS tile of the hub mode: hub tasks are grouped for it
 };
 
 // ---------------------------------------------------------------------------

@@ -202,9 +202,10 @@ void free_graphs_unlocked(std::unique_lock<std::mutex>& lk, std::vector<device_g
 bool launch_round(serve_state* S, int si) {
     slot& s = S->slots[si];
     tc_context_s* ctx = S->ctx;
+    const tc_tuning tun = tuning_snapshot(ctx);
     for (job* j : s.jobs) {
         if (!j->cold) continue;
-        bucket_params bp = params_of(ctx->tuning);
+        bucket_params bp = params_of(tun);
         bp.tri = 0;   // cold graphs live for one round: no forward lists (not in their footprint)
         j->status = build_into(j->n, (int64_t)j->src.size(), j->src.data(), j->dst.data(), j->flags, bp, s.stream,
                                &j->built, nullptr);
@@ -221,7 +222,7 @@ bool launch_round(serve_state* S, int si) {
         }
         const device_graph& g = j->cold ? j->built : j->g->g;
         descs[i] = describe(g);
-        append_items(g, (uint32_t)i, ctx->tuning.tri && g.tri.fwd_ptr, items, rest);
+        append_items(g, (uint32_t)i, tun.tri && g.tri.fwd_ptr, items, rest);
     }
     const uint32_t n_hub = (uint32_t)items.size();
     items.insert(items.end(), rest.begin(), rest.end());     // hub items first
@@ -239,7 +240,7 @@ bool launch_round(serve_state* S, int si) {
             e = hipMemcpyAsync(s.d_num, s.h_num, 2 * sizeof(uint32_t), hipMemcpyHostToDevice, s.stream);
         if (e == hipSuccess)
             e = batch_launch(s.d_desc, s.d_items, s.d_num, s.d_accs, (uint64_t)kNumClasses * s.jobs.size(), s.d_ctr,
-                             ctx->tuning.batch_blocks, ctx->tuning.hub_blocks, s.stream);
+                             tun.batch_blocks, tun.hub_blocks, tun.hub_tile, tun.batch_tile, s.stream);
         if (e == hipSuccess)
             e = hipMemcpyAsync(s.h_accs, s.d_accs, sizeof(unsigned long long) * kNumClasses * s.jobs.size(),
                                hipMemcpyDeviceToHost, s.stream);

@@ -2,9 +2,10 @@
 //
 // Coordinate descent over small candidate grids, two sweeps.  The objective is
 // the wall time of the real census call on the caller's sample: tc_census for
-// a single graph (all three bucket kernels and their grids matter), the
-// captured batched launch for several graphs (thresholds and the persistent
-// grid matter).  Candidates that change thresholds rebucket the sample graphs
+// a single graph (the bucket kernels: thresholds, grids, LDS tiles, group
+// size), the captured batched launch for several graphs (thresholds, the two
+// persistent grids, the hub and batch LDS tiles).  Candidates that change how
+// graphs are bucketed (thresholds, tri, hub tile) rebucket the sample graphs
 // first.  Results are cached in a small JSON file keyed by device, CU count,
 // mode and a coarse degree signature of the sample.  The tuning never changes
 // any count; only which kernel runs each dyad and how many workgroups run.
@@ -12,8 +13,10 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "tc_api_internal.h"
 
@@ -52,32 +55,54 @@ std::string read_file(const char* path) {
     return s;
 }
 
-// The cache is one JSON object: {"<key>": {"t0": .., "t1": .., ...}, ...}
+// The tuning fields, in the order of tc_tuning, with their JSON names.
+struct field_def {
+    const char* name;
+    uint32_t tc_tuning::*field;
+};
+const field_def kFields[] = {
+    {"t0", &tc_tuning::t0}, {"t1", &tc_tuning::t1}, {"lane_blocks", &tc_tuning::lane_blocks},
+    {"wave_blocks", &tc_tuning::wave_blocks}, {"group_blocks", &tc_tuning::group_blocks},
+    {"batch_blocks", &tc_tuning::batch_blocks}, {"t_hub", &tc_tuning::t_hub}, {"hub_blocks", &tc_tuning::hub_blocks},
+    {"tri", &tc_tuning::tri}, {"hub_tile", &tc_tuning::hub_tile}, {"wave_tile", &tc_tuning::wave_tile},
+    {"group_tile", &tc_tuning::group_tile}, {"group_size", &tc_tuning::group_size},
+    {"batch_tile", &tc_tuning::batch_tile},
+};
+
+// The cache is one JSON object: {"<key>": {"t0": .., "t1": .., ...}, ...}; an
+// entry must name every field and pass the same checks as tc_set_tuning.
 bool cache_lookup(const std::string& text, const std::string& key, tc_tuning* t) {
     std::string needle = "\"" + key + "\"";
     size_t p = text.find(needle);
     if (p == std::string::npos) return false;
-    p = text.find('{', p + needle.size());
-    if (p == std::string::npos) return false;
-    unsigned a[6];
-    unsigned b[3];
-    int got = std::sscanf(text.c_str() + p,
-                          "{\"t0\": %u, \"t1\": %u, \"lane_blocks\": %u, \"wave_blocks\": %u, \"group_blocks\": %u, "
-                          "\"batch_blocks\": %u, \"t_hub\": %u, \"hub_blocks\": %u, \"tri\": %u",
-                          &a[0], &a[1], &a[2], &a[3], &a[4], &a[5], &b[0], &b[1], &b[2]);
-    if (got != 9) return false;
-    *t = tc_tuning{a[0], a[1], a[2], a[3], a[4], a[5], b[0], b[1], b[2]};
-    return t->t0 <= t->t1 && a[2] && a[3] && a[4] && a[5] && b[1] && b[2] <= 1;
+    size_t open = text.find('{', p + needle.size());
+    if (open == std::string::npos) return false;
+    size_t close = text.find('}', open);
+    if (close == std::string::npos) return false;
+    const std::string body = text.substr(open, close - open);
+    tc_tuning out{};
+    for (const field_def& f : kFields) {
+        const std::string name = std::string("\"") + f.name + "\":";
+        size_t q = body.find(name);
+        if (q == std::string::npos) return false;
+        char* endp = nullptr;
+        const char* start = body.c_str() + q + name.size();
+        unsigned long v = std::strtoul(start, &endp, 10);
+        if (endp == start || v > 0xffffffffUL) return false;
+        out.*(f.field) = (uint32_t)v;
+    }
+    if (check_tuning(out) != TC_OK) return false;
+    *t = out;
+    return true;
 }
 
 void cache_store(const char* path, const std::string& key, const tc_tuning& t, double seconds) {
     std::string text = read_file(path);
-    char entry[512];
-    std::snprintf(entry, sizeof(entry),
-                  "\"%s\": {\"t0\": %u, \"t1\": %u, \"lane_blocks\": %u, \"wave_blocks\": %u, \"group_blocks\": %u, "
-                  "\"batch_blocks\": %u, \"t_hub\": %u, \"hub_blocks\": %u, \"tri\": %u, \"seconds\": %.6g}",
-                  key.c_str(), t.t0, t.t1, t.lane_blocks, t.wave_blocks, t.group_blocks, t.batch_blocks, t.t_hub,
-                  t.hub_blocks, t.tri, seconds);
+    std::string entry = "\"" + key + "\": {";
+    for (const field_def& f : kFields) entry += std::string("\"") + f.name + "\": " + std::to_string(t.*(f.field)) + ", ";
+    char sec[64];
+    std::snprintf(sec, sizeof(sec), "\"seconds\": %.6g}", seconds);
+    entry += sec;
     size_t close = text.rfind('}');
     std::string out;
     if (text.empty() || close == std::string::npos || text.find('{') == std::string::npos) {
@@ -140,44 +165,48 @@ extern "C" int tc_autotune(tc_context ctx, const tc_graph* sample, int32_t count
     }
     const uint32_t cu = (uint32_t)(ctx->cu_count > 0 ? ctx->cu_count : 256);
     const uint32_t kInf = 0xffffffffu;
-    const std::vector<uint32_t> t0s = {8, 16, 32, 64, 128, 256};
-    const std::vector<uint32_t> t1s = {256, 512, 1024, 2048, 4096, 8192, 16384, kInf};
-    const std::vector<uint32_t> lane = {cu * 4, cu * 8, cu * 16};
-    const std::vector<uint32_t> wave = {cu * 5, cu * 10, cu * 20};
-    const std::vector<uint32_t> group = {cu * 1, cu * 2, cu * 4};
-    const std::vector<uint32_t> batch = {cu * 2, cu * 3, cu * 4, cu * 6};
-    const std::vector<uint32_t> hubt = {32, 64, 128, 256, 512, 1024, 4096, kInf};
-    const std::vector<uint32_t> hubb = {cu * 2, cu * 3, cu * 5, cu * 8};
-    const std::vector<uint32_t> tris = {0, 1};
+    const bool single = count == 1;
+    // The search space: every field the objective depends on, with the values
+    // tried.  Thresholds, tri and the hub tile change how graphs are bucketed
+    // (apply() rebuckets the sample); the rest only change launches.  A single
+    // graph runs the per-bucket kernels (lane / wave / group / hub grids and
+    // tiles); a batch runs the two persistent kernels (batch and hub grids,
+    // batch and hub tiles).
+    struct param {
+        uint32_t tc_tuning::*field;
+        std::vector<uint32_t> values;
+        bool for_single, for_batch;
+    };
+    const param params[] = {
+        {&tc_tuning::tri, {0, 1}, true, true},
+        {&tc_tuning::t1, {256, 512, 1024, 2048, 4096, 8192, 16384, kInf}, true, true},
+        {&tc_tuning::t0, {8, 16, 32, 64, 128, 256}, true, true},
+        {&tc_tuning::t_hub, {32, 64, 128, 256, 512, 1024, 4096, kInf}, true, true},
+        {&tc_tuning::lane_blocks, {cu * 4, cu * 8, cu * 16}, true, false},
+        {&tc_tuning::wave_blocks, {cu * 5, cu * 10, cu * 20}, true, false},
+        {&tc_tuning::group_blocks, {cu * 1, cu * 2, cu * 4}, true, false},
+        {&tc_tuning::batch_blocks, {cu * 2, cu * 3, cu * 4, cu * 6}, false, true},
+        {&tc_tuning::hub_blocks, {cu * 2, cu * 3, cu * 5, cu * 8}, true, true},
+        {&tc_tuning::hub_tile, {512, 1024, 2048}, true, true},
+        {&tc_tuning::wave_tile, {512, 1024, 2048}, true, false},
+        {&tc_tuning::group_tile, {2048, 4096, 8192}, true, false},
+        {&tc_tuning::group_size, {256, 512}, true, false},
+        {&tc_tuning::batch_tile, {512, 1024, 2048}, false, true},
+    };
     const int reps = 3;
 
     rc = apply(ctx, sample, count, best);
     double best_s = 0;
     if (rc == TC_OK) rc = measure(ctx, sample, count, reps, &best_s);
     for (int sweep = 0; sweep < 2 && rc == TC_OK; ++sweep) {
-        for (int param = -1; param < 8 && rc == TC_OK; ++param) {
-            const std::vector<uint32_t>* cands = nullptr;
-            if (param == -1 && count == 1) cands = &tris;   // the batched kernel has no forward-list path
-            if (param == 0) cands = &t1s;
-            if (param == 1) cands = &t0s;
-            if (param == 6) cands = &hubt;
-            if (param == 7 && count == 1) cands = &hubb;
-            if (count == 1) {
-                if (param == 2) cands = &lane;
-                if (param == 3) cands = &wave;
-                if (param == 4) cands = &group;
-            } else if (param == 5) {
-                cands = &batch;
-            }
-            if (!cands) continue;
-            for (uint32_t v : *cands) {
+        for (const param& pr : params) {
+            if (rc != TC_OK) break;
+            if (single ? !pr.for_single : !pr.for_batch) continue;
+            for (uint32_t v : pr.values) {
                 tc_tuning c = best;
-                uint32_t* field = param == -1 ? &c.tri : param == 0 ? &c.t1 : param == 1 ? &c.t0 : param == 2 ? &c.lane_blocks
-                                : param == 3 ? &c.wave_blocks : param == 4 ? &c.group_blocks
-                                : param == 5 ? &c.batch_blocks : param == 6 ? &c.t_hub : &c.hub_blocks;
-                if (*field == v) continue;
-                *field = v;
-                if (c.t0 > c.t1) continue;
+                if (c.*(pr.field) == v) continue;
+                c.*(pr.field) = v;
+                if (check_tuning(c) != TC_OK) continue;
                 rc = apply(ctx, sample, count, c);
                 double s = 0;
                 if (rc == TC_OK) rc = measure(ctx, sample, count, reps, &s);

@@ -73,7 +73,8 @@ class tc_tuning(ctypes.Structure):
     _fields_ = [("t0", ctypes.c_uint32), ("t1", ctypes.c_uint32), ("lane_blocks", ctypes.c_uint32),
                 ("wave_blocks", ctypes.c_uint32), ("group_blocks", ctypes.c_uint32),
                 ("batch_blocks", ctypes.c_uint32), ("t_hub", ctypes.c_uint32), ("hub_blocks", ctypes.c_uint32),
-                ("tri", ctypes.c_uint32)]
+                ("tri", ctypes.c_uint32), ("hub_tile", ctypes.c_uint32), ("wave_tile", ctypes.c_uint32),
+                ("group_tile", ctypes.c_uint32), ("group_size", ctypes.c_uint32), ("batch_tile", ctypes.c_uint32)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -106,25 +106,45 @@ def test_batch_matches_disjoint_union(ctx):
         hu.release()
 
 
+def _best_of(fn, reps=3):
+    best = 1e30
+    for _ in range(reps + 1):
+        t = time.perf_counter()
+        fn()
+        best = min(best, time.perf_counter() - t)
+    return best
+
+
 def test_autotune_keeps_counts_and_caches(ctx):
     pool = small_pool(24, seed=2)
     handles = [ctx.build_graph(g.n, g.src, g.dst) for g in pool]
+    want = np.array([oracle.census(g.n, g.src, g.dst) for g in pool], dtype=np.uint64)
     default = ctx.get_tuning()
     try:
-        want = ctx.census_each(handles)
+        assert ctx.census_each(handles).tolist() == want.tolist()
+        t_default = _best_of(lambda: ctx.census_batch(handles))
         with tempfile.TemporaryDirectory() as tmp:
             path = os.path.join(tmp, "tune.json")
             best = ctx.autotune(handles, path)
             say(f"[gpu] autotuned batch: {best}")
             assert os.path.exists(path)
+            # the search covers the LDS tiles and the persistent grids too
+            text = open(path).read()
+            for key in ("hub_tile", "batch_tile", "hub_blocks", "batch_blocks", "tri"):
+                assert f'"{key}"' in text, key
             assert ctx.census_batch(handles).tolist() == want.tolist()
             assert ctx.census_each(handles).tolist() == want.tolist()
+            # the tuning was only kept when it measured faster (10 % slack for noise)
+            t_tuned = _best_of(lambda: ctx.census_batch(handles))
+            say(f"[gpu] batch default {t_default * 1e3:.3f} ms, tuned {t_tuned * 1e3:.3f} ms")
+            assert t_tuned <= 1.10 * t_default
             ctx.set_tuning(**default)
             again = ctx.autotune(handles, path)   # cache hit
             assert again == best
-            single = ctx.autotune(handles[:1], path)
+            single_graph = handles[-1:]          # the 2500-vertex star: hub dyads
+            single = ctx.autotune(single_graph, path)
             say(f"[gpu] autotuned single: {single}")
-            assert ctx.census(handles[0]).tolist() == want[0].tolist()
+            assert ctx.census(handles[-1]).tolist() == want[-1].tolist()
             assert "single" in open(path).read() and "batch" in open(path).read()
     finally:
         ctx.set_tuning(**default)

@@ -90,11 +90,30 @@ def _gen_serve(i):
 
 
 def generate_pool(fn, count):
-    """Graphs 0..count-1 of a pool, drawn in worker processes (no GPU there)."""
+    """Graphs 0..count-1 of a pool, drawn in spawned worker processes (which
+    never touch the GPU; spawned, not forked, since this process may already
+    hold the HIP runtime)."""
+    import multiprocessing as mp
     from concurrent.futures import ProcessPoolExecutor
     workers = max(1, min(16, os.cpu_count() or 1))
-    with ProcessPoolExecutor(max_workers=workers) as ex:
+    with ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn")) as ex:
         return list(ex.map(fn, range(count), chunksize=max(1, count // (4 * workers))))
+
+
+def kernel_key(name: str, tri: bool, tuning: dict) -> str:
+    """The name rocprofv3 gives the template instance of a census kernel that
+    runs with this tuning (namespace and arguments dropped), as used in the
+    tables under profiles/."""
+    t = "true" if tri else "false"
+    if name == "k_census_hub":
+        return f"k_census_hub<{t}, {tuning['hub_tile']}u>"
+    if name == "k_census_wave":
+        return f"k_census_wave<{t}, {tuning['wave_tile']}>"
+    if name == "k_census_group":
+        return f"k_census_group<{t}, {tuning['group_size']}, {tuning['group_tile']}>"
+    if name == "k_census_lane":
+        return f"k_census_lane<{t}>"
+    return name
 
 
 def census_bytes(info: dict, n: int, tri: bool) -> float:
@@ -115,21 +134,41 @@ def census_bytes(info: dict, n: int, tri: bool) -> float:
     return (base + 4.0 * sum(cost[:3]) + 8.0 * sum(recs[:3]) + 4.0 * (stream + staged) + 8.0 * recs[3])
 
 
-def bench_batch(args):
-    """Batched census of a pool of uneven R-MAT graphs: one persistent launch
-    (captured HIP graph, autotuned thresholds) against one launch sequence per
-    graph, on the same resident graphs."""
+def golden_counts(kind: str, pool):
+    """The oracle's stored census of every pool graph (tests/golden/, written by
+    the CPU oracle), after checking each graph's arc hash; None when the pool is
+    not the stored one (another size)."""
+    from tests.golden import make_goldens as goldens
+    try:
+        gold = goldens.load(kind)
+    except OSError:
+        return None
+    if len(gold) < len(pool):
+        return None
+    out = []
+    for g, rec in zip(pool, gold):
+        if (g.n, g.m, goldens.arc_hash(g.src, g.dst)) != (rec["n"], rec["m"], rec["hash"]):
+            return None
+        out.append(rec["counts"])
+    return out
+
+
+def run_batch(args, autotune_sample: int) -> dict:
+    """Batched census of the pool of uneven R-MAT graphs: one persistent launch
+    (captured HIP graph) against one launch sequence per graph, on the same
+    resident graphs; every graph's counts against the oracle's stored census."""
     from paper_1603_02655_amd import tc
     log(f"[bench] generating {args.batch_count} batch graphs")
     pool = generate_pool(_gen_batch, args.batch_count)
+    gold = golden_counts("batch", pool)
     ctx = tc.Context(0)
-    log("[bench] building")
+    log("[bench] building the batch pool")
     hs = [ctx.build_graph(g.n, g.src, g.dst) for g in pool]
     arcs = sum(int(h.info["arcs_kept"]) for h in hs)
     rng = np.random.default_rng(1)
     tune_s = 0.0
-    if args.autotune_sample > 0:
-        sample = [hs[i] for i in rng.choice(len(hs), size=min(args.autotune_sample, len(hs)), replace=False)]
+    if autotune_sample > 0:
+        sample = [hs[i] for i in rng.choice(len(hs), size=min(autotune_sample, len(hs)), replace=False)]
         t = time.perf_counter()
         tuning = ctx.autotune(sample)
         tune_s = time.perf_counter() - t
@@ -150,52 +189,69 @@ def bench_batch(args):
     ctx.reset_kernel_stats()
     ctx.set_timing(True)
     tc.device_synchronize(0)
+    steps = max(1, args.batch_steps)
     t = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         out = ctx.census_batch(hs)
     tc.device_synchronize(0)
     el = time.perf_counter() - t
     ks = ctx.kernel_stats()
     ctx.set_timing(False)
     assert out.tolist() == each.tolist()
-    step_s = el / args.steps
+    equal_oracle = None if gold is None else out.tolist() == gold
+    step_s = el / steps
     launch_ms = ks["batch_ms"] / max(1, ks["batch_launches"])
     tri = bool(ctx.get_tuning()["tri"])
     bytes_alg = sum(census_bytes(h.info, h.n, tri and h.info["fwd_entries"] > 0) for h in hs)
     achieved = bytes_alg / (launch_ms / 1000.0) / 1e9 if launch_ms > 0 else 0.0
-    line = {
-        "metric": "census arcs/sec (batched)", "value": arcs / step_s, "unit": "arcs/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1000 * step_s, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "u32/u64", "data": "synthetic",
-        "config": {"workload": f"batch of {len(hs)} R-MAT digraphs, n log-uniform [50, 20000], "
-                               "mean out-degree U[3,30], reciprocity 0.10", "graphs": len(hs), "arcs": arcs,
-                   "tuning": tuning},
-        "graphs_per_s": len(hs) / step_s,
-        "per_graph_launches": {"graphs_per_s": len(hs) / each_s, "arcs_per_s": arcs / each_s,
-                               "ms": 1000 * each_s},
+    res = {
+        "workload": f"batch of {len(hs)} R-MAT digraphs, n log-uniform [50, 20000], mean out-degree U[3,30], "
+                    "reciprocity 0.10",
+        "graphs": len(hs), "arcs": arcs, "steps": steps, "ms_per_batch": 1000 * step_s,
+        "arcs_per_s": arcs / step_s, "graphs_per_s": len(hs) / step_s,
+        "per_graph_launches": {"graphs_per_s": len(hs) / each_s, "arcs_per_s": arcs / each_s, "ms": 1000 * each_s},
         "speedup_vs_per_graph": each_s / step_s,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_census_batch",
+                     "frac": achieved / HBM_PEAK_GBS, "kernel": "k_census_batch_hub + k_census_batch",
                      "kernel_ms": launch_ms, "bytes_per_launch": bytes_alg},
+        "tuning": tuning, "autotune_s": tune_s,
         "path": "forward-list triangles" if tri else "dyad intersections",
-        "autotune_s": tune_s,
+        "results_equal_oracle": equal_oracle,
     }
     for h in hs:
         h.release()
     ctx.close()
+    if equal_oracle is False:
+        raise SystemExit("batched counts differ from the oracle's stored census")
+    return res
+
+
+def bench_batch(args):
+    res = run_batch(args, args.autotune_sample)
+    line = {
+        "metric": "census arcs/sec (batched)", "value": res["arcs_per_s"], "unit": "arcs/s", "n_gpus": 1,
+        "steps": res["steps"], "warmup": args.warmup, "ms_per_step": res["ms_per_batch"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u32/u64", "data": "synthetic",
+        "config": {"workload": res["workload"], "graphs": res["graphs"], "arcs": res["arcs"],
+                   "tuning": res["tuning"]},
+    }
+    line.update({k: v for k, v in res.items() if k not in ("workload", "graphs", "arcs", "tuning", "steps")})
     print(json.dumps(line), flush=True)
 
 
-def bench_serve(args):
+def run_serve(args) -> dict:
     """Served census: Poisson arrivals of requests for graphs of a resident
-    pool; results checked against the same graphs' census run alone."""
+    pool; every result against the same graph's census run alone and, for the
+    stored pool, against the oracle's census."""
     from paper_1603_02655_amd import tc
     log(f"[bench] generating serving pool of {args.pool}")
     pool = generate_pool(_gen_serve, args.pool)
+    gold = golden_counts("serve", pool)
     ctx = tc.Context(0)
     hs = [ctx.build_graph(g.n, g.src, g.dst) for g in pool]
     arcs = np.array([int(h.info["arcs_kept"]) for h in hs])
     alone = ctx.census_each(hs)
+    equal_oracle = None if gold is None else alone.tolist() == gold
     # per-graph launch baseline over a random request sequence
     rng = np.random.default_rng(5)
     seq = rng.integers(0, len(hs), 200)
@@ -264,26 +320,36 @@ def bench_serve(args):
                      "rounds": st["rounds"], "mean_admission_ms": st["mean_admission_ms"],
                      "results_equal_alone": ok})
         log(f"[bench] rate {rate}: {runs[-1]}")
-    head = runs[-1]
+    res = {
+        "workload": f"serving pool of {len(hs)} graphs (even ER, odd R-MAT r=0.10), n log-uniform "
+                    "[1e3, 1e6], mean out-degree U[4,32]; Poisson arrivals",
+        "duration_s": args.duration, "pool_arcs": int(arcs.sum()), "runs": runs,
+        "per_graph_launches_rps": base_rps,
+        # at the first (nominal) rate: latency; at the last: what the loop sustains
+        "requests_per_s": runs[0]["completed_per_s"], "p50_ms": runs[0]["p50_ms"], "p99_ms": runs[0]["p99_ms"],
+        "capacity_rps": runs[-1]["completed_per_s"], "capacity_arcs_per_s": runs[-1]["achieved_arcs_per_s"],
+        "results_equal_alone": all_ok, "results_equal_oracle": equal_oracle,
+    }
+    for h in hs:
+        h.release()
+    ctx.close()
+    if not all_ok or equal_oracle is False:
+        raise SystemExit("served counts differ from the census alone or from the oracle's stored census")
+    return res
+
+
+def bench_serve(args):
+    res = run_serve(args)
+    head = res["runs"][0]
     line = {
         "metric": "served census throughput + p50/p99 latency", "value": head["completed_per_s"],
         "unit": "requests/s", "n_gpus": 1, "steps": head["requests"], "warmup": 0,
         "ms_per_step": head["p50_ms"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "u32/u64", "data": "synthetic",
-        "config": {"workload": f"serving pool of {len(hs)} graphs (even ER, odd R-MAT r=0.10), n log-uniform "
-                               "[1e3, 1e6], mean out-degree U[4,32]; Poisson arrivals",
-                   "duration_s": args.duration, "pool_arcs": int(arcs.sum())},
-        "runs": runs,
-        "per_graph_launches_rps": base_rps,
-        "results_equal_alone": all_ok,
+        "config": {"workload": res["workload"], "duration_s": res["duration_s"], "pool_arcs": res["pool_arcs"]},
     }
-    ok = all_ok
-    for h in hs:
-        h.release()
-    ctx.close()
+    line.update({k: v for k, v in res.items() if k not in ("workload", "duration_s", "pool_arcs")})
     print(json.dumps(line), flush=True)
-    if not ok:
-        sys.exit(1)
 
 
 def copy_calibration(nbytes: int):
@@ -346,8 +412,10 @@ def cpu_tuned(g0, m_kept: int) -> dict:
             "census_s": secs}
 
 
-def dyad_work(g0):
-    """Per-vertex canonical-dyad work sum(|N(u)|+|N(v)|) (for the CPU sample)."""
+def oracle_work(g0):
+    """Per-vertex work of the oracle's census (entries it visits): for vertex x
+    its own row once, and for every neighbour p > x the row of x twice and the
+    row of p three times.  Used only to extrapolate the timed CPU sample."""
     n = g0.n
     s = g0.src.astype(np.int64)
     d = g0.dst.astype(np.int64)
@@ -356,37 +424,39 @@ def dyad_work(g0):
     hi = np.maximum(s[keep], d[keep])
     pk = np.unique(lo * n + hi)
     a, b = pk // n, pk % n
-    deg = np.bincount(a, minlength=n) + np.bincount(b, minlength=n)
-    return np.bincount(a, weights=(deg[a] + deg[b]).astype(np.float64), minlength=n)
+    deg = (np.bincount(a, minlength=n) + np.bincount(b, minlength=n)).astype(np.float64)
+    return deg + np.bincount(a, weights=2.0 * deg[a] + 3.0 * deg[b], minlength=n)
 
 
 def cpu_baseline(g0, m_kept: int, seconds: float):
-    """The oracle (test infrastructure) on a bounded sample: threads take
-    consecutive vertex ranges (task queues) of the same graph until the time
-    budget is spent; the work rate is extrapolated to the whole graph."""
+    """The oracle (test infrastructure) on a bounded sample: the vertices are
+    cut into chunks of about equal oracle work, threads take chunks in a random
+    order (each chunk one call of the oracle's range census) until the time
+    budget is spent, and the work rate is extrapolated to the whole graph."""
     import oracle
     threads = max(1, min(16, os.cpu_count() or 1))
-    work = dyad_work(g0)
+    work = oracle_work(g0)
     total_work = float(work.sum())
     cum = np.concatenate([[0.0], np.cumsum(work)])
-    chunk = 2e6
+    cuts = np.unique(np.searchsorted(cum, np.linspace(0.0, total_work, 4097), side="left").clip(0, g0.n))
+    chunks = [(int(a), int(b)) for a, b in zip(cuts[:-1], cuts[1:]) if b > a]
+    order = np.random.default_rng(0).permutation(len(chunks))
     og = oracle.OracleGraph(g0.n, g0.src, g0.dst)
     lock = threading.Lock()
-    state = {"u": int(np.random.default_rng(0).integers(0, g0.n // 2)), "work": 0.0}
+    state = {"next": 0, "work": 0.0, "chunks": 0}
     deadline = time.perf_counter() + seconds
 
     def worker():
         while time.perf_counter() < deadline:
             with lock:
-                u0 = state["u"]
-                if u0 >= g0.n:
+                if state["next"] >= len(order):
                     return
-                u1 = int(np.searchsorted(cum, cum[u0] + chunk, side="right")) - 1
-                u1 = max(u0 + 1, min(g0.n, u1))
-                state["u"] = u1
+                u0, u1 = chunks[order[state["next"]]]
+                state["next"] += 1
             og.census_range(u0, u1)
             with lock:
                 state["work"] += cum[u1] - cum[u0]
+                state["chunks"] += 1
 
     t0 = time.perf_counter()
     ts = [threading.Thread(target=worker) for _ in range(threads)]
@@ -399,9 +469,9 @@ def cpu_baseline(g0, m_kept: int, seconds: float):
     rate = state["work"] / el
     full_s = total_work / rate
     return {"value": m_kept / full_s, "unit": "arcs/s", "cores": threads, "kind": "oracle",
-            "sample": (f"task-queue vertex ranges covering {state['work']:.3g} of {total_work:.3g} "
-                       f"dyad-work units (sum |N(u)|+|N(v)|) in {el:.1f} s; rate extrapolated to the "
-                       f"whole graph ({full_s:.0f} s)")}
+            "sample": (f"{state['chunks']} of {len(chunks)} vertex-range chunks taken in random order, "
+                       f"{state['work']:.3g} of {total_work:.3g} oracle work units (row entries visited) in "
+                       f"{el:.1f} s; rate extrapolated to the whole graph ({full_s:.0f} s)")}
 
 
 def main():
@@ -413,11 +483,15 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch-count", type=int, default=4096)
-    ap.add_argument("--rate", default="2000", help="comma-separated arrival rates (requests/s)")
+    ap.add_argument("--rate", default="2000,8000",
+                    help="comma-separated arrival rates (requests/s); the last one measures capacity")
     ap.add_argument("--duration", type=float, default=5.0)
     ap.add_argument("--pool", type=int, default=64)
-    ap.add_argument("--autotune-sample", type=int, default=256,
+    ap.add_argument("--batch-steps", type=int, default=10, help="timed batched launches")
+    ap.add_argument("--autotune-sample", type=int, default=0,
                     help="graphs the batched bench autotunes on (0: keep the default tuning)")
+    ap.add_argument("--single-only", action="store_true",
+                    help="default workload: leave out the batched and served legs")
     ap.add_argument("--tuning", default="", help="comma-separated key=value overrides, e.g. t_hub=256")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="also run 3 device-to-device copies of this many bytes (counter calibration)")
@@ -495,6 +569,7 @@ def main():
     bytes_dom = bytes_of[dom_name]
     achieved = bytes_dom / (dom_ms / 1000.0) / 1e9 if dom_ms > 0 else 0.0
     b_alg = 4.0 * info["sum_d2"] + 8.0 * (info["asym_dyads"] + info["mutual_dyads"]) + 4.0 * (g0.n + 1)
+    step_bytes = census_bytes(info, g0.n, tri)
     line = {
         "metric": "census arcs/sec",
         "value": value,
@@ -514,8 +589,7 @@ def main():
                    "tuning": ctx.get_tuning()},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(args.workload, dom_name + ("<true>" if tri else "<false>")
-                                                 if dom_name != "k_census_totals" else dom_name),
+                     "traffic": measured_traffic(args.workload, kernel_key(dom_name, tri, ctx.get_tuning())),
                      "kernel": dom_name, "bytes_per_launch": bytes_dom, "kernel_ms": dom_ms,
                      "source_hash": census_source_hash()},
         "path": "forward-list triangles" if tri else "dyad intersections",
@@ -523,8 +597,12 @@ def main():
         "kernel_bytes": bytes_of,
         "step_ms": {"p10": float(np.percentile(step_ms, 10)), "p50": float(np.percentile(step_ms, 50)),
                     "p90": float(np.percentile(step_ms, 90))},
-        "b_alg_gb": b_alg / 1e9,
-        "census_gbs_alg": b_alg / (el / args.steps) / 1e9,
+        # the survey's per-dyad merge byte count, for reference only: the
+        # forward-list path never moves most of it
+        "merge_b_alg_gb": b_alg / 1e9,
+        # every kernel of the step by its own byte model, over the whole step
+        "step_roofline": {"bytes": step_bytes, "achieved": step_bytes / (el / args.steps) / 1e9,
+                          "unit": "GB/s", "frac": step_bytes / (el / args.steps) / 1e9 / HBM_PEAK_GBS},
         "build_s": build_s,
         "counts": [int(x) for x in counts],
     }
@@ -536,13 +614,20 @@ def main():
         bw = copy_bandwidth()
         line["roofline"]["copy_gbs"] = bw
         line["roofline"]["frac_of_copy"] = achieved / bw
+    gold = golden_counts("rmat", [g0]) if args.workload == "rmat" else None
+    line["counts_equal_oracle"] = None if gold is None else line["counts"] == gold[0]
+    g.release()
+    ctx.close()
+    if line["counts_equal_oracle"] is False:
+        raise SystemExit("census differs from the oracle's stored census")
+    if args.workload == "rmat" and not args.single_only:
+        line["batched"] = run_batch(args, args.autotune_sample)
+        line["served"] = run_serve(args)
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")
         line["cpu_baseline"] = cpu_baseline(g0, m_kept, args.cpu_seconds)
         log("[bench] tuned multicore CPU census (context)")
         line["cpu_tuned"] = cpu_tuned(g0, m_kept)
-    g.release()
-    ctx.close()
     print(json.dumps(line), flush=True)
 
 

@@ -99,8 +99,10 @@ typedef struct {
  * triangle once, as a shared vertex of the forward lists of its two first
  * vertices; the same thresholds bucket those edge records by
  * |N+(x)| + |N+(y)| (and t_hub by the longer forward list).  The counts are
- * identical either way.  tc_census_range, the batched and the served modes
- * always use the dyad records. */
+ * identical either way.  The batched and the served modes take the same path
+ * per graph (forward-list items for graphs that have forward lists while tri
+ * is set, dyad-record items otherwise; requests that carry their arcs are built
+ * without forward lists).  tc_census_range always uses the dyad records. */
 typedef struct {
     uint32_t t0, t1;
     uint32_t lane_blocks;    /* grid cap, lane kernel (256-thread blocks) */
@@ -151,7 +153,12 @@ int tc_context_create(int device, uint64_t hbm_budget_bytes, void* hip_stream, t
 int tc_context_destroy(tc_context ctx);
 
 /* Builds a resident device graph from m arcs src[i] -> dst[i] (0-based int32
- * ids in [0, n)).  src/dst are read during the call only; host pointers unless
+ * ids in [0, n)): the input G = [V, E] of section "Triad Census Algorithm",
+ * read as a strict digraph with E a set.  On the device: the neighbour rows
+ * N(u) with the direction of every joined pair (what the loop's IsEdge and
+ * IsNeighbour ask), the canonical dyads u < v bucketed by |N(u)| + |N(v)| - 2
+ * (figure "Canonical Dyad (uniform distr.)"), and, when the tuning has tri = 1,
+ * the degree-ordered forward lists.  src/dst are read during the call only; host pointers unless
  * TC_BUILD_DEVICE_PTRS.  Loops and repeated arcs are dropped (counted in info)
  * unless TC_BUILD_STRICT, which rejects them.  Errors: TC_ERR_ARG (null pointer,
  * n < 0, m < 0, id out of range, strict violation), TC_ERR_RANGE (n too large),
@@ -165,7 +172,11 @@ int tc_graph_get_info(tc_context ctx, tc_graph g, tc_graph_info* info);
 /* Frees g.  TC_ERR_BUSY while tickets that use g are pending. */
 int tc_graph_release(tc_context ctx, tc_graph g);
 
-/* Synchronous census: counts[16] (host) receives the 16 class counts of g. */
+/* Synchronous census: counts[16] (host) receives the 16 class counts of g,
+ * the census array of section "Triad Census Algorithm" (figure "Subquadratic
+ * Triad Census Algorithm": per canonical dyad the n - |S| - 2 dyadic triads and
+ * the triads of the third vertices it counts; the null class as C(n,3) minus
+ * the rest).  Errors: TC_ERR_ARG (null or unknown handle), TC_ERR_DEVICE. */
 int tc_census(tc_context ctx, tc_graph g, uint64_t counts[16]);
 
 /* Labelled 64-class census: counts[64] (host) receives the histogram of the

@@ -68,6 +68,29 @@ def measured_traffic(workload_key: str, kernel: str):
     return None
 
 
+def measured_valu_busy(workload_key: str, kernel: str):
+    """VALU busy fraction of `kernel` (SQ_ACTIVE_INST_VALU x 4 cycles over the
+    1024 SIMDs' active cycles) from profiles/sq_counters_<workload>.md, when
+    that table was taken on the current sources; None otherwise."""
+    import re
+    path = os.path.join(ROOT, "profiles", f"sq_counters_{workload_key}.md")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        text = f.read()
+    m = re.search(r"Source hash `([0-9a-f]+)`", text)
+    if not m or m.group(1) != census_source_hash():
+        return None
+    for line in text.splitlines():
+        cells = [c.strip() for c in line.strip().strip("|").split("|")]
+        if len(cells) == 7 and cells[0] == kernel:
+            try:
+                return float(cells[3])
+            except ValueError:
+                return None
+    return None
+
+
 def workload(name: str):
     from paper_1603_02655_amd import synth
     if name == "rmat":
@@ -591,7 +614,9 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic(args.workload, kernel_key(dom_name, tri, ctx.get_tuning())),
                      "kernel": dom_name, "bytes_per_launch": bytes_dom, "kernel_ms": dom_ms,
-                     "source_hash": census_source_hash()},
+                     "source_hash": census_source_hash(),
+                     # what the counters say limits the kernel (SQ_ACTIVE_INST_VALU x 4 / SIMD cycles)
+                     "valu_busy": measured_valu_busy(args.workload, kernel_key(dom_name, tri, ctx.get_tuning()))},
         "path": "forward-list triangles" if tri else "dyad intersections",
         "kernels_ms": per_launch_ms,
         "kernel_bytes": bytes_of,

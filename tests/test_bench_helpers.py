@@ -44,14 +44,37 @@ def test_measured_traffic_only_for_the_current_sources(tmp_path, monkeypatch):
 
 
 def test_committed_traffic_tables_parse():
-    # every row of the committed tables has a 16-digit hash and a byte count
-    for name in ("hbm_traffic_rmat.md", "hbm_traffic_citation.md"):
+    # every row of the committed traffic tables has a 16-digit hash and a byte count
+    for name in ("hbm_traffic_rmat.md", "hbm_traffic_citation.md", "hbm_traffic_batch.md"):
         path = os.path.join(bench.ROOT, "profiles", name)
-        rows = [ln for ln in open(path) if ln.startswith("| k_census")]
+        rows = [ln for ln in open(path) if ln.startswith("| k_census") and ln.count("|") == 8]
         assert rows, name
         for ln in rows:
             cells = [c.strip().strip("`") for c in ln.strip().strip("|").split("|")]
             assert len(cells) == 7 and len(cells[1]) == 16 and float(cells[6]) > 0
+
+
+def test_measured_valu_busy_only_for_the_current_sources(tmp_path, monkeypatch):
+    root = _fake_tree(tmp_path, "int g() { return 0; }\n")
+    monkeypatch.setattr(bench, "ROOT", str(root))
+    h = bench.census_source_hash()
+    (root / "profiles").mkdir()
+    row = "| k_census_hub<true, 1024u> | 2.0 | 4.5e+06 | 0.97 | 0.47 | 0.36 | 0.21 |\n"
+    (root / "profiles" / "sq_counters_rmat.md").write_text(f"Source hash `{h}`.\n\n" + row)
+    (root / "profiles" / "sq_counters_citation.md").write_text("Source hash `0123456789abcdef`.\n\n" + row)
+    assert bench.measured_valu_busy("rmat", "k_census_hub<true, 1024u>") == 0.97
+    assert bench.measured_valu_busy("rmat", "k_census_lane<true>") is None
+    assert bench.measured_valu_busy("citation", "k_census_hub<true, 1024u>") is None   # other sources
+    assert bench.measured_valu_busy("batch", "k_census_hub<true, 1024u>") is None      # no table
+
+
+def test_kernel_key_names_the_template_instance():
+    t = {"hub_tile": 2048, "wave_tile": 512, "group_size": 512, "group_tile": 8192}
+    assert bench.kernel_key("k_census_hub", True, t) == "k_census_hub<true, 2048u>"
+    assert bench.kernel_key("k_census_wave", False, t) == "k_census_wave<false, 512>"
+    assert bench.kernel_key("k_census_group", True, t) == "k_census_group<true, 512, 8192>"
+    assert bench.kernel_key("k_census_lane", True, t) == "k_census_lane<true>"
+    assert bench.kernel_key("k_census_totals", True, t) == "k_census_totals"
 
 
 def test_census_bytes_model():

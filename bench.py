@@ -157,6 +157,12 @@ def census_bytes(info: dict, n: int, tri: bool) -> float:
     return (base + 4.0 * sum(cost[:3]) + 8.0 * sum(recs[:3]) + 4.0 * (stream + staged) + 8.0 * recs[3])
 
 
+def apply_tuning(ctx, args):
+    """--tuning key=value overrides on top of the library's default tuning."""
+    if args.tuning:
+        ctx.set_tuning(**{k: int(v) for k, v in (kv.split("=") for kv in args.tuning.split(","))})
+
+
 def golden_counts(kind: str, pool):
     """The oracle's stored census of every pool graph (tests/golden/, written by
     the CPU oracle), after checking each graph's arc hash; None when the pool is
@@ -185,6 +191,7 @@ def run_batch(args, autotune_sample: int) -> dict:
     pool = generate_pool(_gen_batch, args.batch_count)
     gold = golden_counts("batch", pool)
     ctx = tc.Context(0)
+    apply_tuning(ctx, args)
     log("[bench] building the batch pool")
     hs = [ctx.build_graph(g.n, g.src, g.dst) for g in pool]
     arcs = sum(int(h.info["arcs_kept"]) for h in hs)
@@ -271,6 +278,7 @@ def run_serve(args) -> dict:
     pool = generate_pool(_gen_serve, args.pool)
     gold = golden_counts("serve", pool)
     ctx = tc.Context(0)
+    apply_tuning(ctx, args)
     hs = [ctx.build_graph(g.n, g.src, g.dst) for g in pool]
     arcs = np.array([int(h.info["arcs_kept"]) for h in hs])
     alone = ctx.census_each(hs)
@@ -534,8 +542,7 @@ def main():
     log(f"[bench] generating workload {args.workload}")
     g0 = workload(args.workload)
     ctx = tc.Context(0)
-    if args.tuning:
-        ctx.set_tuning(**{k: int(v) for k, v in (kv.split("=") for kv in args.tuning.split(","))})
+    apply_tuning(ctx, args)
     log(f"[bench] building n={g0.n} m={g0.m}")
     t = time.perf_counter()
     g = ctx.build_graph(g0.n, g0.src, g0.dst)

@@ -610,8 +610,17 @@ __device__ inline uint32_t find_first_ge(const uint32_t* __restrict__ nbr, uint3
 
 // Geometry of one LDS tile of TILE anchor entries (the tunable hub tile): a
 // hash table of TILE / 2 buckets of 4 slots (mean load 2 entries) and a filter
-// of 8 bits per staged entry.
-constexpr uint32_t kHubFilterMul = 0x85EBCA6Bu;          // filter hash (another multiplier than the buckets')
+// of 8 bits per staged entry.  Both hash a key (m << 23) | w (m the task's
+// place in its group, w the vertex) folded to 24 bits, w + (m << 20), with a
+// 24 x 24-bit multiply and keep the top bits of the low 32 bits of the
+// product (a full 32-bit multiply issues at a quarter of the rate).  Only the
+// placement depends on the hash: a probe compares whole keys.
+constexpr uint32_t kHubBucketMul = 0x9E3779u;            // odd 24-bit multipliers
+constexpr uint32_t kHubFilterMul = 0x85EBCBu;
+__device__ inline uint32_t hub_fold(uint32_t key) { return (key & ((1u << 23) - 1u)) + ((key >> 23) << 20); }
+// Low 32 bits of the product of the low 24 bits of a and b, unsigned (HIP's
+// __umul24 returns a signed int, whose right shifts would be arithmetic).
+__device__ inline uint32_t mul24(uint32_t a, uint32_t b) { return (uint32_t)__umul24(a, b); }
 template <uint32_t TILE>
 struct hub_geom {
     static constexpr uint32_t kBuckets = TILE / 2;
@@ -622,9 +631,9 @@ struct hub_geom {
     static constexpr uint32_t kFilterBits = 1u << kFilterLog;
     static_assert((TILE & (TILE - 1)) == 0 && TILE >= 256 && TILE <= 4096, "power-of-two tile");
     static_assert(kFilterBits / 32 >= (uint32_t)kHubB / 8, "filter words");
-    __device__ static inline uint32_t bucket(uint32_t w) { return (w * 0x9E3779B1u) >> (32 - kBucketBits); }
-    // bit of a vertex in the tile's filter
-    __device__ static inline uint32_t filter_bit(uint32_t w) { return (w * kHubFilterMul) >> kFilterShift; }
+    // from a folded key
+    __device__ static inline uint32_t bucket_of(uint32_t fold) { return mul24(fold, kHubBucketMul) >> (32 - kBucketBits); }
+    __device__ static inline uint32_t filter_bit_of(uint32_t fold) { return mul24(fold, kHubFilterMul) >> kFilterShift; }
 };
 
 // Buckets fill their slots in order, so a bucket whose last slot is empty
@@ -632,7 +641,7 @@ struct hub_geom {
 template <uint32_t TILE>
 __device__ inline void hub_insert(uint32_t* hash, uint32_t e) {
     using G = hub_geom<TILE>;
-    uint32_t b = G::bucket(e >> 2);
+    uint32_t b = G::bucket_of(hub_fold(e >> 2));
     for (;;) {
         for (uint32_t s = 0; s < 4; ++s)
             if (atomicCAS(&hash[4 * b + s], kEmpty, e) == kEmpty) return;
@@ -642,12 +651,12 @@ __device__ inline void hub_insert(uint32_t* hash, uint32_t e) {
 
 // The whole bucket is read at once and its four slots compared without
 // branches (a vertex is stored at most once); the next bucket is read only
-// when this one is full and holds no match.
+// when this one is full and holds no match.  w is the key, fold its folded form.
 template <uint32_t TILE>
-__device__ inline uint32_t hub_probe(const uint32_t* hash, uint32_t w) {
+__device__ inline uint32_t hub_probe(const uint32_t* hash, uint32_t w, uint32_t fold) {
     using G = hub_geom<TILE>;
     const uint4* h4 = reinterpret_cast<const uint4*>(hash);
-    uint32_t b = G::bucket(w);
+    uint32_t b = G::bucket_of(fold);
     for (;;) {
         const uint4 q = h4[b];
         uint32_t r = kEmpty;
@@ -699,15 +708,11 @@ __device__ inline void block_scan_u32(uint32_t* a, uint32_t count, uint32_t* wsu
 // What a shared vertex w of the dyad (or edge record) (u, v), u < v, adds to
 // the census depends only on the direction bits f = f_uv, fa = f_uw, fb = f_vw
 // (each 1, 2 or 3: the pairs are joined) and on where w lies: below u, between
-// u and v, or above v.  The hub mode counts shared vertices per such signature
-// (81 of them) in one 32-bit LDS histogram per workgroup and turns the counts
-// into class updates when it flushes.
-constexpr uint32_t kSigs = 81;
-
-__device__ inline uint32_t shared_sig(uint32_t w, uint32_t u, uint32_t v, uint32_t f, uint32_t fa, uint32_t fb) {
-    const uint32_t where = w > v ? 2u : (w > u ? 1u : 0u);
-    return (f - 1u) + 3u * (fa - 1u) + 9u * (fb - 1u) + 27u * where;
-}
+// u and v, or above v (where = [w > u] + [w > v]).  The hub mode counts shared
+// vertices per signature f | fa << 2 | fb << 4 | where << 6 (192 slots, 81 of
+// them reachable) in one 32-bit LDS histogram per workgroup and turns the
+// counts into class updates when it flushes.
+constexpr uint32_t kSigs = 192;
 
 // Scales every update of one signature by its count.
 template <class H>
@@ -730,10 +735,11 @@ __device__ inline uint32_t hub_blocks(uint32_t p0, uint32_t p1) {
 constexpr uint32_t kHubRing = 128;   // candidates a wavefront holds between probe rounds
 struct hub_lds {
     uint32_t* hash;   // hub_geom::kSlots, 16-byte aligned
-    uint2* ring;      // kHubRing x (kHubB / 64) candidates: (entry, meta word of its record)
+    uint32_t* ring_e; // kHubRing x (kHubB / 64) candidates: the entry
+    uint32_t* ring_m; // ... and the meta word of its record
     uint32_t* pos;    // next unprobed position in the other endpoint's row
     uint32_t* end;    // end of that row's entries in the current tile
-    uint32_t* meta;   // (x << 3) | (anchor is u) << 2 | f_uv
+    uint32_t* meta;   // (m << 26) | (x << 3) | (anchor is u) << 2 | f_uv, m the task's place in its group
     uint32_t* off;    // blocks of this tile, then their exclusive scan and kScanPad copies of the total
     uint32_t* wsum;   // 4 words
     uint32_t* sig;    // kSigs counts shared by the workgroup
@@ -754,11 +760,10 @@ constexpr uint32_t hub_lds_words() {
 
 // Wavefronts per SIMD the hub kernels are compiled for: seven (the best
 // measured with 1024-entry tiles), or as many workgroups as the LDS of a CU
-// (160 KiB) holds for larger tiles.
+// (160 KiB) holds for larger tiles (the kernels' other LDS takes < 256 bytes).
 template <uint32_t TILE>
 constexpr uint32_t hub_waves_per_simd() {
-    return (163840u / (4u * hub_lds_words<TILE>() + 1024u)) < 7u ? (163840u / (4u * hub_lds_words<TILE>() + 1024u))
-                                                                 : 7u;
+    return (163840u / (4u * hub_lds_words<TILE>() + 256u)) < 7u ? (163840u / (4u * hub_lds_words<TILE>() + 256u)) : 7u;
 }
 
 template <uint32_t TILE>
@@ -766,7 +771,8 @@ __device__ inline hub_lds hub_carve(uint32_t* base) {
     uint32_t* p = base;
     hub_lds S;
     S.hash = p;  p += hub_geom<TILE>::kSlots;
-    S.ring = reinterpret_cast<uint2*>(p);  p += 2 * kHubRing * (kHubB / 64);
+    S.ring_e = p;  p += kHubRing * (kHubB / 64);
+    S.ring_m = p;  p += kHubRing * (kHubB / 64);
     S.pos = p;   p += kHubChunk;
     S.end = p;   p += kHubChunk;
     S.meta = p;  p += kHubChunk;
@@ -790,7 +796,8 @@ __device__ inline void hub_bins_flush(const hub_lds& S, const uint8_t* T, H& h) 
         const uint32_t c = S.sig[k];
         if (c == 0) continue;
         S.sig[k] = 0;
-        const uint32_t f = 1u + k % 3u, fa = 1u + (k / 3u) % 3u, fb = 1u + (k / 9u) % 3u, where = k / 27u;
+        const uint32_t f = k & 3u, fa = (k >> 2) & 3u, fb = (k >> 4) & 3u, where = k >> 6;
+        if (f == 0 || fa == 0 || fb == 0) continue;   // never counted
         // ids that put w below u, between u and v, or above v
         const uint32_t u = 1u, v = 3u, w = where * 2u;
         scaled_bins<H> sh{h, (unsigned long long)c};
@@ -848,7 +855,7 @@ __device__ inline void hub_group_run(uint32_t js, uint32_t M, const dyad_rec* __
             while (m + 1 < M && eb[m + 1] <= f) ++m;
             const uint32_t v = nbr[S.tk[kTkHb + js + m] + (f - eb[m])];
             hub_insert<TILE>(S.hash, (m << 25) | v);
-            const uint32_t fb = G::filter_bit((m << 23) | (v >> 2));
+            const uint32_t fb = G::filter_bit_of(hub_fold((m << 23) | (v >> 2)));
             atomicOr(&S.filt[fb >> 5], 1u << (fb & 31u));
         }
         if (multi_tile) {
@@ -889,24 +896,26 @@ __device__ inline void hub_group_run(uint32_t js, uint32_t M, const dyad_rec* __
         const uint32_t lane = tid & 63u, wid = tid >> 6;
         constexpr uint32_t kWaves = kHubB / 64;
         const uint32_t q0 = (uint32_t)(((uint64_t)P * wid) / kWaves), q1 = (uint32_t)(((uint64_t)P * (wid + 1)) / kWaves);
-        uint2* ring = S.ring + wid * kHubRing;
+        uint32_t* ring_e = S.ring_e + wid * kHubRing;
+        uint32_t* ring_m = S.ring_m + wid * kHubRing;
         uint32_t cnt = 0;   // the same on every lane: ring[0, cnt) waits to be probed
         // Probes ring[l] on the lanes l < c (c <= 64): a hit adds one to the
-        // count of its signature.
+        // count of its signature.  The hit's direction bits fh are relative
+        // to the anchor a, the candidate's fx to the other endpoint x; the
+        // anchor is u (then fa = fh, fb = fx) or v (fa = fx, fb = fh).
         auto probe_round = [&](uint32_t c) {
             wave_sync{}();
             if (lane < c) {
-                const uint2 q = ring[lane];
-                const uint32_t w = q.x >> 2, m = q.y >> 26;
-                const uint32_t hit = hub_probe<TILE>(S.hash, (m << 23) | w);
+                const uint32_t qe = ring_e[lane], qm = ring_m[lane];
+                const uint32_t w = qe >> 2, mm = qm >> 26;
+                const uint32_t hit = hub_probe<TILE>(S.hash, (mm << 23) | w, w + (mm << 20));
                 if (hit != kEmpty) {
-                    const uint32_t a = S.tk[kTkAnchor + js + m];
-                    const uint32_t x = (q.y >> 3) & ((1u << 23) - 1u), fuv = q.y & 3u;
-                    const bool anchor_u = (q.y & 4u) != 0;
-                    const uint32_t u = anchor_u ? a : x, v = anchor_u ? x : a;
-                    const uint32_t fx = q.x & 3u, fh = hit & 3u;
-                    const uint32_t fa = anchor_u ? fh : fx, fb = anchor_u ? fx : fh;
-                    atomicAdd(&S.sig[shared_sig(w, u, v, fuv, fa, fb)], 1u);
+                    const uint32_t a = S.tk[kTkAnchor + js + mm];
+                    const uint32_t x = (qm >> 3) & ((1u << 23) - 1u);
+                    const uint32_t sx = (qm & 4u) ? 4u : 2u;
+                    const uint32_t code = (qm & 3u) | ((qe & 3u) << sx) | ((hit & 3u) << (6u - sx));
+                    const uint32_t where = (w > a ? 1u : 0u) + (w > x ? 1u : 0u);
+                    atomicAdd(&S.sig[code | (where << 6)], 1u);
                 }
             }
             wave_sync{}();
@@ -925,50 +934,47 @@ __device__ inline void hub_group_run(uint32_t js, uint32_t M, const dyad_rec* __
             uint32_t next = S.off[i + 1], p0 = S.pos[i], p1 = S.end[i], m = S.meta[i];
             uint32_t bb = p0 / kHubGather - S.off[i];   // block of flattened index f: bb + f (mod 2^32)
             for (uint32_t win = q0; win < q1; win += 64u) {
-                const uint32_t f = win + lane;
-                uint32_t e[kHubGather], vm = 0;   // the block's words; bit k: word k is an entry of the row
-#pragma unroll
-                for (uint32_t k = 0; k < kHubGather; ++k) e[k] = 0;
-                if (f < q1) {
+                // lanes past the quarter's end read its last block and keep no entry of it
+                const uint32_t f = min(win + lane, q1 - 1u);
+                if (f >= next) {
+                    // The record of f from the next four record starts
+                    // (off[nrec ..] = P > f past the last record), and by
+                    // bisection when it lies further ahead.
+                    const uint32_t o2 = S.off[i + 2], o3 = S.off[i + 3], o4 = S.off[i + 4], o5 = S.off[i + 5];
+                    i += 1u + (f >= o2 ? 1u : 0u) + (f >= o3 ? 1u : 0u) + (f >= o4 ? 1u : 0u) + (f >= o5 ? 1u : 0u);
+                    next = S.off[i + 1];
                     if (f >= next) {
-                        // The record of f from the next four record starts
-                        // (off[nrec ..] = P > f past the last record), and by
-                        // bisection when it lies further ahead.
-                        const uint32_t o2 = S.off[i + 2], o3 = S.off[i + 3], o4 = S.off[i + 4], o5 = S.off[i + 5];
-                        i += 1u + (f >= o2 ? 1u : 0u) + (f >= o3 ? 1u : 0u) + (f >= o4 ? 1u : 0u) + (f >= o5 ? 1u : 0u);
-                        next = S.off[i + 1];
-                        if (f >= next) {
-                            uint32_t hi = nrec;
-                            while (hi - i > 1) {
-                                const uint32_t mid = (i + hi) >> 1;
-                                if (S.off[mid] <= f) i = mid; else hi = mid;
-                            }
-                            next = S.off[i + 1];
+                        uint32_t hi = nrec;
+                        while (hi - i > 1) {
+                            const uint32_t mid = (i + hi) >> 1;
+                            if (S.off[mid] <= f) i = mid; else hi = mid;
                         }
-                        p0 = S.pos[i];
-                        p1 = S.end[i];
-                        m = S.meta[i];
-                        bb = p0 / kHubGather - S.off[i];
+                        next = S.off[i + 1];
                     }
-                    const uint32_t b0 = (bb + f) * kHubGather;   // first entry of the block: b0 < p1, p0 < b0 + 8
-                    const uint4* src = reinterpret_cast<const uint4*>(nbr + b0);
-                    const uint4 lo4 = src[0], hi4 = src[1];
-                    e[0] = lo4.x; e[1] = lo4.y; e[2] = lo4.z; e[3] = lo4.w;
-                    e[4] = hi4.x; e[5] = hi4.y; e[6] = hi4.z; e[7] = hi4.w;
-                    const uint32_t klo = p0 > b0 ? p0 - b0 : 0u, khi = min(p1 - b0, kHubGather);
-                    vm = ((1u << khi) - 1u) & ~((1u << klo) - 1u);
+                    p0 = S.pos[i];
+                    p1 = S.end[i];
+                    m = S.meta[i];
+                    bb = p0 / kHubGather - S.off[i];
                 }
-                // Filter: the word of every entry first, then the bits.  The
-                // filter of a key k has bit (k * C) >> kFilterShift set.
-                const uint32_t mkey = (m >> 26) << 23;
+                const uint32_t b0 = (bb + f) * kHubGather;   // first entry of the block: b0 < p1, p0 < b0 + 8
+                const uint4* src = reinterpret_cast<const uint4*>(nbr + b0);
+                const uint4 lo4 = src[0], hi4 = src[1];
+                const uint32_t e[kHubGather] = {lo4.x, lo4.y, lo4.z, lo4.w, hi4.x, hi4.y, hi4.z, hi4.w};
+                const uint32_t klo = p0 > b0 ? p0 - b0 : 0u, khi = min(p1 - b0, kHubGather);
+                // bit k: word k is an entry of the row (none past the quarter's end)
+                const uint32_t vm = win + lane < q1 ? ((1u << khi) - 1u) & ~((1u << klo) - 1u) : 0u;
+                // Filter: the word of every entry first, then the bits, at
+                // bit (fold * C) >> kFilterShift of the folded key
+                // (e >> 2) + (m << 20) = (e + (m << 22)) >> 2.
+                const uint32_t m22 = (m >> 26) << 22;
                 uint32_t hk[kHubGather], fw[kHubGather], pm = 0;
 #pragma unroll
                 for (uint32_t k = 0; k < kHubGather; ++k) {
-                    hk[k] = (mkey | (e[k] >> 2)) * kHubFilterMul;
-                    fw[k] = S.filt[hk[k] >> (G::kFilterShift + 5)];
+                    hk[k] = mul24((e[k] + m22) >> 2, kHubFilterMul) >> G::kFilterShift;
+                    fw[k] = S.filt[hk[k] >> 5];
                 }
 #pragma unroll
-                for (uint32_t k = 0; k < kHubGather; ++k) pm |= ((fw[k] >> ((hk[k] >> G::kFilterShift) & 31u)) & 1u) << k;
+                for (uint32_t k = 0; k < kHubGather; ++k) pm |= ((fw[k] >> (hk[k] & 31u)) & 1u) << k;
                 pm &= vm;
                 // appends: the entries that pass go to ring[cnt ..] in lane order
 #pragma unroll
@@ -978,17 +984,24 @@ __device__ inline void hub_group_run(uint32_t js, uint32_t M, const dyad_rec* __
                     if (pass) {
                         const uint32_t r = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
                                                                      __builtin_amdgcn_mbcnt_lo((uint32_t)bal, cnt));
-                        ring[r] = make_uint2(e[k], m);
+                        ring_e[r] = e[k];
+                        ring_m[r] = m;
                     }
                     cnt += (uint32_t)__popcll(bal);
                     if (cnt >= 64u) {
                         probe_round(64u);
                         cnt -= 64u;
                         // the rest moves to the front
-                        uint2 t = make_uint2(0u, 0u);
-                        if (lane < cnt) t = ring[64u + lane];
+                        uint32_t te = 0, tm = 0;
+                        if (lane < cnt) {
+                            te = ring_e[64u + lane];
+                            tm = ring_m[64u + lane];
+                        }
                         wave_sync{}();
-                        if (lane < cnt) ring[lane] = t;
+                        if (lane < cnt) {
+                            ring_e[lane] = te;
+                            ring_m[lane] = tm;
+                        }
                     }
                 }
             }

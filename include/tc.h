@@ -138,8 +138,11 @@ typedef struct {
     uint64_t submitted, completed, rounds;
     uint64_t resident_graphs;
     uint64_t bytes_in_flight;
-    double p50_ms, p99_ms;         /* submit -> completion latency */
+    double p50_ms, p99_ms;         /* submit -> completion latency of the admitted requests
+                                      (histogram with 64 buckets per decade: within 3.7 %) */
     double mean_admission_ms;      /* submit -> admission wait */
+    uint64_t failed_rounds;        /* rounds whose launch failed (their tickets carry the error) */
+    uint64_t abandoned_rounds;     /* rounds that ran past the watchdog (tickets: TC_ERR_DEVICE) */
 } tc_serve_stats;
 
 /* Creates a context on HIP device `device`.  hbm_budget_bytes bounds the device
@@ -250,6 +253,12 @@ int tc_poll(tc_context ctx, tc_ticket ticket, uint64_t counts[16], int* done);
  * TC_ERR_SHUTDOWN, later submissions fail with TC_ERR_SHUTDOWN.  The context
  * stays usable for synchronous calls. */
 int tc_serve_stop(tc_context ctx);
+
+/* Watchdog of the serving loop: a round still running ms milliseconds after
+ * its launch fails its tickets with TC_ERR_DEVICE, and its stream slot is not
+ * used again (when every slot is lost, queued and new tickets fail with
+ * TC_ERR_DEVICE).  Default 60000.  TC_ERR_ARG unless ms > 0. */
+int tc_serve_set_watchdog_ms(tc_context ctx, double ms);
 
 /* Serving statistics since the context was created (or last reset). */
 int tc_serve_get_stats(tc_context ctx, tc_serve_stats* out);

@@ -11,7 +11,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD_DIR = os.path.join(PKG, "_build")
 LIB_PATH = os.path.join(PKG, "libtc.so")
-SOURCES = ["tc_build.hip", "tc_census.hip", "tc_api.hip", "tc_batch.hip", "tc_serve.cpp", "tc_tune.cpp"]
+SOURCES = ["tc_build.hip", "tc_census.hip", "tc_api.hip", "tc_batch.hip", "tc_sched.cpp", "tc_serve.cpp", "tc_tune.cpp"]
 ARCH = "gfx950"
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -50,6 +50,7 @@ struct tc_context_s {
     unsigned long long* host_many = nullptr;  // pinned read-back area of tc_census_each_noalloc
     tc::batch_plan* batch = nullptr;    // cached batched launch (captured hipGraph), owned
     tc::serve_state* serve = nullptr;   // serving loop, started on first submit, owned
+    double watchdog_ms = 0;             // serving watchdog (0: the default)
 };
 
 namespace tc {

@@ -90,7 +90,8 @@ class tc_kernel_stats(ctypes.Structure):
 class tc_serve_stats(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64), ("rounds", ctypes.c_uint64),
                 ("resident_graphs", ctypes.c_uint64), ("bytes_in_flight", ctypes.c_uint64),
-                ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double), ("mean_admission_ms", ctypes.c_double)]
+                ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double), ("mean_admission_ms", ctypes.c_double),
+                ("failed_rounds", ctypes.c_uint64), ("abandoned_rounds", ctypes.c_uint64)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -117,6 +118,7 @@ SIGNATURES = {
     "tc_submit_arcs": (ctypes.c_int, [_vp, _i32, _i64, _vp, _vp, _u32, _P(_u64)]),
     "tc_poll": (ctypes.c_int, [_vp, _u64, _vp, _P(ctypes.c_int)]),
     "tc_serve_stop": (ctypes.c_int, [_vp]),
+    "tc_serve_set_watchdog_ms": (ctypes.c_int, [_vp, ctypes.c_double]),
     "tc_serve_get_stats": (ctypes.c_int, [_vp, _P(tc_serve_stats)]),
     "tc_serve_reset_stats": (ctypes.c_int, [_vp]),
     "tc_set_tuning": (ctypes.c_int, [_vp, _P(tc_tuning)]),
@@ -337,6 +339,9 @@ class Context:
 
     def serve_stop(self):
         _check(load().tc_serve_stop(self.handle), "tc_serve_stop")
+
+    def serve_set_watchdog_ms(self, ms: float):
+        _check(load().tc_serve_set_watchdog_ms(self.handle, float(ms)), "tc_serve_set_watchdog_ms")
 
     def serve_stats(self) -> dict:
         s = tc_serve_stats()

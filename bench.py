@@ -157,6 +157,29 @@ def census_bytes(info: dict, n: int, tri: bool) -> float:
     return (base + 4.0 * sum(cost[:3]) + 8.0 * sum(recs[:3]) + 4.0 * (stream + staged) + 8.0 * recs[3])
 
 
+def time_shards(ctx, g, full_counts, shard_counts, reps: int = 5) -> dict:
+    """Per-shard census times on this one GPU: the work one GPU of a G-GPU run
+    would do, without the graph's broadcast and the final 128-byte sum.  Each
+    shard's wall time is the median of `reps` calls; the shards' counts must
+    add up to the full census."""
+    out = {}
+    for G in shard_counts:
+        ms, total = [], np.zeros(16, np.uint64)
+        for k in range(G):
+            t = []
+            for _ in range(reps):
+                ts = time.perf_counter()
+                p = ctx.census_shard(g, k, G)
+                t.append(1000.0 * (time.perf_counter() - ts))
+            ms.append(float(np.median(t)))
+            with np.errstate(over="ignore"):
+                total = total + p.astype(np.uint64)
+        if total[1:].tolist() != [int(x) for x in full_counts[1:]]:
+            raise SystemExit(f"the {G} shard censuses do not add up to the full census")
+        out[str(G)] = {"max_ms": max(ms), "min_ms": min(ms), "sum_ms": sum(ms)}
+    return out
+
+
 def apply_tuning(ctx, args):
     """--tuning key=value overrides on top of the library's default tuning."""
     if args.tuning:
@@ -646,6 +669,7 @@ def main():
         bw = copy_bandwidth()
         line["roofline"]["copy_gbs"] = bw
         line["roofline"]["frac_of_copy"] = achieved / bw
+    line["shards"] = time_shards(ctx, g, counts, (2, 4, 8))
     gold = golden_counts("rmat", [g0]) if args.workload == "rmat" else None
     line["counts_equal_oracle"] = None if gold is None else line["counts"] == gold[0]
     g.release()

@@ -200,6 +200,20 @@ int tc_census64(tc_context ctx, tc_graph g, uint64_t counts[64]);
  * summing the partials of a partition of [0, n) gives counts[1..15]. */
 int tc_census_range(tc_context ctx, tc_graph g, int32_t u_begin, int32_t u_end, uint64_t partial[16]);
 
+/* Shard `shard` of `nshards` of the census of g, on the path tc_census takes:
+ * each bucket's records (dyads, or forward-list edge records), the hub task
+ * groups and the neighbour entries of the per-dyad totals pass are cut into
+ * nshards contiguous ranges of equal length and this call runs range `shard`
+ * of each; every record, task group and entry falls in exactly one shard.
+ * This is the unit of work a multi-GPU census would give one GPU (section
+ * "Future work": distribute the canonical dyads).  partial[0] is 0; the other
+ * counts are exact modulo 2^64 (a shard may hold only one side of a dyad's
+ * terms, so a single partial can wrap), and their sum over the nshards shards,
+ * modulo 2^64, is counts[1..15] of tc_census; 003 follows as C(n,3) minus the
+ * rest.  Errors: TC_ERR_ARG (null or unknown handle, nshards < 1, shard
+ * outside [0, nshards)), TC_ERR_DEVICE. */
+int tc_census_shard(tc_context ctx, tc_graph g, int32_t shard, int32_t nshards, uint64_t partial[16]);
+
 /* Census of `count` resident graphs in one persistent launch, replayed from a
  * captured HIP graph when the same set of graphs is passed again.
  * counts (host) receives count*16 values, graph i at counts[16*i]. */

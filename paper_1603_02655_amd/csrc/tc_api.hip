@@ -451,6 +451,35 @@ int tc_census_range(tc_context ctx, tc_graph g, int32_t u_begin, int32_t u_end, 
     return TC_OK;
 }
 
+int tc_census_shard(tc_context ctx, tc_graph g, int32_t shard, int32_t nshards, uint64_t partial[16]) {
+    if (!ctx || !g || !partial || nshards < 1 || shard < 0 || shard >= nshards) return TC_ERR_ARG;
+    if (hipSetDevice(ctx->device) != hipSuccess) return TC_ERR_DEVICE;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    if (!ctx->graphs.count(g)) return TC_ERR_ARG;
+    const device_graph& dg = g->g;
+    unsigned long long raw[16] = {0};
+    if (dg.p > 0) {
+        const bool tri = ctx->tuning.tri && dg.tri.fwd_ptr;
+        census_slices sl = full_slices(dg, tri);
+        const uint64_t k = (uint64_t)shard, G = (uint64_t)nshards;
+        for (int b = 0; b < kBucketHub; ++b) {
+            const uint64_t lo = sl.begin[b], len = sl.end[b] - sl.begin[b];
+            sl.begin[b] = lo + len * k / G;
+            sl.end[b] = lo + len * (k + 1) / G;
+        }
+        const uint64_t ng = tri ? dg.tri.edges.n_groups : dg.n_hub_groups;
+        sl.hub_g0 = (uint32_t)(ng * k / G);
+        sl.hub_g1 = (uint32_t)(ng * (k + 1) / G);
+        sl.totals_begin = dg.U * k / G;
+        sl.totals_end = dg.U * (k + 1) / G;
+        int rc = run_census_locked(ctx, dg, sl, raw, 0, tri);
+        if (rc != TC_OK) return rc;
+    }
+    partial[0] = 0;
+    for (int c = 1; c < kNumClasses; ++c) partial[c] = raw[c];
+    return TC_OK;
+}
+
 int tc_census_each(tc_context ctx, const tc_graph* graphs, int32_t count, uint64_t* counts) {
     if (!ctx || count < 0 || (count > 0 && (!graphs || !counts))) return TC_ERR_ARG;
     if (hipSetDevice(ctx->device) != hipSuccess) return TC_ERR_DEVICE;

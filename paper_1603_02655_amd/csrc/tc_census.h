@@ -20,12 +20,16 @@ struct census_config {
 bool tile_supported(uint32_t hub_tile, uint32_t wave_tile, uint32_t group_tile, uint32_t group_size,
                     uint32_t batch_tile);
 
-// Per-bucket dyad slices [begin, end) into g.dyads (merge buckets); the hub
-// bucket always runs all its tasks, restricted to dyads with u in [u_lo, u_hi).
+// Per-bucket record slices [begin, end) into g.dyads or the edge records
+// (merge buckets); the hub bucket runs its task groups [hub_g0, hub_g1),
+// restricted to dyads with u in [u_lo, u_hi); the totals pass of the
+// forward-list path covers the neighbour entries [totals_begin, totals_end).
 struct census_slices {
     uint64_t begin[kBuckets];
     uint64_t end[kBuckets];
     uint32_t u_lo = 0, u_hi = 0xffffffffu;
+    uint32_t hub_g0 = 0, hub_g1 = 0xffffffffu;
+    uint64_t totals_begin = 0, totals_end = ~0ull;
 };
 
 // ---- batched launch over many graphs ----

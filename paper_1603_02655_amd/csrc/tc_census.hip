@@ -382,11 +382,12 @@ __device__ inline void slots_flush(unsigned long long* sbins, const uint32_t* bi
     for (uint32_t k = threadIdx.x; k < kTotalsSlots * kLaneB; k += kLaneB) sbins[k] = 0;
 }
 
+// Over the neighbour entries [e0, e1).
 __global__ __launch_bounds__(kLaneB) void k_census_totals(const uint32_t* __restrict__ nbr,
                                                           const uint32_t* __restrict__ owner,
                                                           const uint4* __restrict__ rinfo,
-                                                          const uint64_t* __restrict__ tpre, uint64_t U, uint64_t n,
-                                                          const uint8_t* __restrict__ table,
+                                                          const uint64_t* __restrict__ tpre, uint64_t e0, uint64_t e1,
+                                                          uint64_t n, const uint8_t* __restrict__ table,
                                                           unsigned long long* __restrict__ acc) {
     __shared__ unsigned long long sbins[kTotalsSlots * kLaneB];
     __shared__ unsigned long long wbins[wave_bins<kLaneB>::kWords];
@@ -402,15 +403,15 @@ __global__ __launch_bounds__(kLaneB) void k_census_totals(const uint32_t* __rest
     const uint32_t nslots = s_nslots;
     if (nslots) {
         slot_bins hs{sbins};
-        for (uint64_t base = (uint64_t)blockIdx.x * kLaneB * kTotalsPer; base < U;
+        for (uint64_t base = e0 + (uint64_t)blockIdx.x * kLaneB * kTotalsPer; base < e1;
              base += (uint64_t)gridDim.x * kLaneB * kTotalsPer)
-            totals_entries<kTotalsPer, kLaneB>(base, U, nbr, owner, rinfo, tpre, n, TS, hs);
+            totals_entries<kTotalsPer, kLaneB>(base, e1, nbr, owner, rinfo, tpre, n, TS, hs);
         global_bins g{acc};
         slots_flush(sbins, bin_of_slot, nslots, g);
     } else {
-        for (uint64_t base = (uint64_t)blockIdx.x * kLaneB * kTotalsPer; base < U;
+        for (uint64_t base = e0 + (uint64_t)blockIdx.x * kLaneB * kTotalsPer; base < e1;
              base += (uint64_t)gridDim.x * kLaneB * kTotalsPer)
-            totals_entries<kTotalsPer, kLaneB>(base, U, nbr, owner, rinfo, tpre, n, T, hw);
+            totals_entries<kTotalsPer, kLaneB>(base, e1, nbr, owner, rinfo, tpre, n, T, hw);
         hw.flush(acc);
     }
 }
@@ -1076,7 +1077,8 @@ __device__ inline void hub_chunk_run(const hub_task* __restrict__ tasks, uint32_
 template <bool Tri, uint32_t TILE>
 __global__ __launch_bounds__(kHubB)
 __attribute__((amdgpu_waves_per_eu(hub_waves_per_simd<TILE>(), hub_waves_per_simd<TILE>()))) void k_census_hub(
-    census_args L, const hub_task* __restrict__ tasks, uint32_t ntasks, uint32_t ngroups, unsigned int* ctr) {
+    census_args L, const hub_task* __restrict__ tasks, uint32_t ntasks, uint32_t ngroups, uint32_t g0, uint32_t g1,
+    unsigned int* ctr) {
     __shared__ __attribute__((aligned(16))) uint32_t hub_words[hub_lds_words<TILE>()];
     __shared__ unsigned long long bins[block_bins<kHubB>::kWords];
     __shared__ uint8_t T[64];
@@ -1089,12 +1091,13 @@ __attribute__((amdgpu_waves_per_eu(hub_waves_per_simd<TILE>(), hub_waves_per_sim
     __syncthreads();
     uint32_t since = 0;
     const uint32_t xcd = blockIdx.x % kXcds;
-    if (threadIdx.x == 0) s_next = take_chunk(ctr, xcd);
+    // task groups g0 + k, k taken from the counters, below g1 (<= ngroups)
+    if (threadIdx.x == 0) s_next = g0 + take_chunk(ctr, xcd);
     __syncthreads();
     uint32_t c = s_next;
     __syncthreads();
-    while (c < ngroups) {
-        if (threadIdx.x == 0) s_next = take_chunk(ctr, xcd);
+    while (c < g1) {
+        if (threadIdx.x == 0) s_next = g0 + take_chunk(ctr, xcd);
         const uint32_t t0 = tasks[c].group, t1 = c + 1 < ngroups ? tasks[c + 1].group : ntasks;
         hub_chunk_run<Tri, TILE>(tasks, t0, t1, L.dyads, L.nbr, L.tpre, L.n, L.u_lo, L.u_hi, S, T, h, since);
         c = s_next;
@@ -1378,17 +1381,18 @@ void launch_bucket(int b, const census_args& L, uint64_t cnt, const census_confi
     }
 }
 
+// Task groups [g0, g1) of the ngroups.
 template <bool Tri>
-void launch_hub(const census_args& L, const hub_task* tasks, uint32_t ntasks, uint32_t ngroups,
-                const census_config& cfg, unsigned int* counters, hipStream_t s) {
-    const dim3 grid((uint32_t)std::min<uint64_t>(ngroups, cfg.hub_blocks));
+void launch_hub(const census_args& L, const hub_task* tasks, uint32_t ntasks, uint32_t ngroups, uint32_t g0,
+                uint32_t g1, const census_config& cfg, unsigned int* counters, hipStream_t s) {
+    const dim3 grid((uint32_t)std::min<uint64_t>(g1 - g0, cfg.hub_blocks));
     unsigned int* c = counters + 3 * kXcds;
     if (cfg.hub_tile == 512)
-        hipLaunchKernelGGL((k_census_hub<Tri, 512>), grid, dim3(kHubB), 0, s, L, tasks, ntasks, ngroups, c);
+        hipLaunchKernelGGL((k_census_hub<Tri, 512>), grid, dim3(kHubB), 0, s, L, tasks, ntasks, ngroups, g0, g1, c);
     else if (cfg.hub_tile == 1024)
-        hipLaunchKernelGGL((k_census_hub<Tri, 1024>), grid, dim3(kHubB), 0, s, L, tasks, ntasks, ngroups, c);
+        hipLaunchKernelGGL((k_census_hub<Tri, 1024>), grid, dim3(kHubB), 0, s, L, tasks, ntasks, ngroups, g0, g1, c);
     else
-        hipLaunchKernelGGL((k_census_hub<Tri, 2048>), grid, dim3(kHubB), 0, s, L, tasks, ntasks, ngroups, c);
+        hipLaunchKernelGGL((k_census_hub<Tri, 2048>), grid, dim3(kHubB), 0, s, L, tasks, ntasks, ngroups, g0, g1, c);
 }
 
 }  // namespace
@@ -1405,6 +1409,9 @@ hipError_t census_launch(const device_graph& g, const census_slices& sl, bool tr
     const hub_task* tasks = tri ? g.tri.edges.tasks : g.hub_tasks;
     const uint32_t ntasks = tri ? g.tri.edges.n_tasks : g.n_hub_tasks;
     const uint32_t ngroups = tri ? g.tri.edges.n_groups : g.n_hub_groups;
+    const uint32_t hg0 = std::min(sl.hub_g0, ngroups), hg1 = std::max(hg0, std::min(sl.hub_g1, ngroups));
+    const uint64_t te0 = std::min<uint64_t>(sl.totals_begin, g.U);
+    const uint64_t te1 = std::max(te0, std::min<uint64_t>(sl.totals_end, g.U));
     // (only when the hub kernel has more to stream than the totals pass)
     const bool beside = tri && side != nullptr && fork != nullptr && g.tri.edges.stream > g.U;
     if (tri) {
@@ -1419,17 +1426,17 @@ hipError_t census_launch(const device_graph& g, const census_slices& sl, bool tr
             ts = side;
         }
         if (ev) (void)hipEventRecord(ev[2 * kBuckets], ts);
-        if (g.U > 0) {
-            uint32_t grid = (uint32_t)std::min<uint64_t>((g.U + kTotalsPer * kLaneB - 1) / (kTotalsPer * kLaneB),
-                                                         beside ? cfg.side_blocks : cfg.lane_blocks);
-            hipLaunchKernelGGL(k_census_totals, dim3(grid), dim3(kLaneB), 0, ts, g.nbr, g.owner, g.rinfo, g.tpre,
-                               g.U, (uint64_t)g.n, table, acc);
+        if (te1 > te0) {
+            uint32_t grid = (uint32_t)std::min<uint64_t>(
+                (te1 - te0 + kTotalsPer * kLaneB - 1) / (kTotalsPer * kLaneB), beside ? cfg.side_blocks : cfg.lane_blocks);
+            hipLaunchKernelGGL(k_census_totals, dim3(grid), dim3(kLaneB), 0, ts, g.nbr, g.owner, g.rinfo, g.tpre, te0,
+                               te1, (uint64_t)g.n, table, acc);
         }
         if (ev) (void)hipEventRecord(ev[2 * kBuckets + 1], ts);
     }
     for (int b = 0; b < kBuckets; ++b) {
         uint64_t cnt = sl.end[b] > sl.begin[b] ? sl.end[b] - sl.begin[b] : 0;
-        if (b == kBucketHub) cnt = ntasks;
+        if (b == kBucketHub) cnt = hg1 - hg0;
         // beside the hub kernel, the lane bucket follows the totals pass on the side stream
         const hipStream_t bs = beside && b == 0 ? side : s;
         if (ev) (void)hipEventRecord(ev[2 * b], bs);
@@ -1438,8 +1445,8 @@ hipError_t census_launch(const device_graph& g, const census_slices& sl, bool tr
                           table};
             if (b == kBucketHub) {
                 L.dyads = recs;
-                if (tri) launch_hub<true>(L, tasks, ntasks, ngroups, cfg, counters, s);
-                else launch_hub<false>(L, tasks, ntasks, ngroups, cfg, counters, s);
+                if (tri) launch_hub<true>(L, tasks, ntasks, ngroups, hg0, hg1, cfg, counters, s);
+                else launch_hub<false>(L, tasks, ntasks, ngroups, hg0, hg1, cfg, counters, s);
             } else if (tri) {
                 launch_bucket<true>(b, L, cnt, cfg, counters, bs);
             } else {

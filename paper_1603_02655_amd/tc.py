@@ -110,6 +110,7 @@ SIGNATURES = {
     "tc_graph_release": (ctypes.c_int, [_vp, _vp]),
     "tc_census": (ctypes.c_int, [_vp, _vp, _vp]),
     "tc_census_range": (ctypes.c_int, [_vp, _vp, _i32, _i32, _vp]),
+    "tc_census_shard": (ctypes.c_int, [_vp, _vp, _i32, _i32, _vp]),
     "tc_census64": (ctypes.c_int, [_vp, _vp, _vp]),
     "tc_census_batch": (ctypes.c_int, [_vp, _vp, _i32, _vp]),
     "tc_census_each": (ctypes.c_int, [_vp, _vp, _i32, _vp]),
@@ -294,6 +295,12 @@ class Context:
     def census_range(self, g: Graph, u0: int, u1: int) -> np.ndarray:
         out = _u64_out(16)
         _check(load().tc_census_range(self.handle, g.handle, int(u0), int(u1), out.ctypes.data), "tc_census_range")
+        return out
+
+    def census_shard(self, g: Graph, shard: int, nshards: int) -> np.ndarray:
+        out = _u64_out(16)
+        _check(load().tc_census_shard(self.handle, g.handle, int(shard), int(nshards), out.ctypes.data),
+               "tc_census_shard")
         return out
 
     def _many(self, fn, graphs):

@@ -226,6 +226,42 @@ def test_range_partition_sums_to_full(ctx):
         og.close()
 
 
+def _sum_shards(ctx, g, nshards):
+    parts = [ctx.census_shard(g, k, nshards) for k in range(nshards)]
+    for p in parts:
+        assert int(p[0]) == 0
+    # partials are exact modulo 2^64: add them as uint64, wrapping
+    with np.errstate(over="ignore"):
+        return np.sum(np.stack(parts).astype(np.uint64), axis=0, dtype=np.uint64)
+
+
+def test_shards_sum_to_full(ctx):
+    g0 = synth.rmat_digraph(1 << 14, 1 << 18, synth.rng_for(74, 0), reciprocity=0.2)
+    g = ctx.build_graph(g0.n, g0.src, g0.dst)
+    default = ctx.get_tuning()
+    try:
+        full = ctx.census(g)
+        assert triads.identity_violations(g0.n, g0.src, g0.dst, full) == []
+        for tri, t_hub in ((1, default["t_hub"]), (1, 0), (0, default["t_hub"]), (0, 0)):
+            ctx.set_tuning(**dict(default, tri=tri, t_hub=t_hub))
+            ctx.rebucket(g)
+            info = g.info
+            say(f"[gpu] shards tri={tri} t_hub={t_hub} hub_groups={info['hub_groups']} "
+                f"tri_groups={info['tri_groups']}")
+            if t_hub == 0:
+                assert (info["tri_groups"] if tri else info["hub_groups"]) > 8
+            for nshards in (1, 3, 8, 61):
+                s = _sum_shards(ctx, g, nshards)
+                assert s[1:].tolist() == full[1:].tolist(), (tri, t_hub, nshards)
+        for bad in ((0, 0), (-1, 2), (2, 2)):
+            with pytest.raises(tc.TcError):
+                ctx.census_shard(g, *bad)
+    finally:
+        ctx.set_tuning(**default)
+        ctx.rebucket(g)
+        g.release()
+
+
 def test_info_counts(ctx):
     src = [0, 0, 1, 2, 2, 3, 3]
     dst = [1, 1, 0, 2, 3, 2, 0]
@@ -327,6 +363,8 @@ def test_full_size_identities_and_sampled_ranges(ctx, which):
         assert [int(x) for x in full] == gold["counts"]
         assert triads.identity_violations(g0.n, g0.src, g0.dst, full) == []
         assert ctx.census(g).tolist() == full.tolist()
+        say(f"[gpu] shards {which}")
+        assert _sum_shards(ctx, g, 8)[1:].tolist() == full[1:].tolist()
         rng = np.random.default_rng(5)
         for u0, u1 in _ranges_with_work(g0, 2e7, 3, rng):
             say(f"[gpu] range {which} [{u0},{u1})")

@@ -611,30 +611,36 @@ __device__ inline uint32_t find_first_ge(const uint32_t* __restrict__ nbr, uint3
 
 // Geometry of one LDS tile of TILE anchor entries (the tunable hub tile): a
 // hash table of TILE / 2 buckets of 4 slots (mean load 2 entries) and a filter
-// of 8 bits per staged entry.  Both hash a key (m << 23) | w (m the task's
-// place in its group, w the vertex) folded to 24 bits, w + (m << 20), with a
-// 24 x 24-bit multiply and keep the top bits of the low 32 bits of the
-// product (a full 32-bit multiply issues at a quarter of the rate).  Only the
-// placement depends on the hash: a probe compares whole keys.
+// of 8 bits per staged entry.  The table hashes a key (m << 23) | w (m the
+// task's place in its group, w the vertex) folded to 24 bits, w + (m << 20),
+// with a 24 x 24-bit multiply and keeps the top bits of the low 32 bits of the
+// product (a full 32-bit multiply issues at a quarter of the rate).  The
+// filter position of (m, w) is w * C + mix(m) (one multiply-add, mix(m)
+// computed once per record): its top bits pick the filter word and its low
+// five bits the bit, which is the shift count a 32-bit shift takes as it is.
+// Only the placement depends on the hashes: a probe compares whole keys.
 constexpr uint32_t kHubBucketMul = 0x9E3779u;            // odd 24-bit multipliers
 constexpr uint32_t kHubFilterMul = 0x85EBCBu;
+constexpr uint32_t kHubMemberMul = 0x9E3779B1u;          // odd 32-bit multiplier of the member index
 __device__ inline uint32_t hub_fold(uint32_t key) { return (key & ((1u << 23) - 1u)) + ((key >> 23) << 20); }
 // Low 32 bits of the product of the low 24 bits of a and b, unsigned (HIP's
 // __umul24 returns a signed int, whose right shifts would be arithmetic).
 __device__ inline uint32_t mul24(uint32_t a, uint32_t b) { return (uint32_t)__umul24(a, b); }
+__device__ inline uint32_t hub_member_mix(uint32_t m) { return m * kHubMemberMul; }
 template <uint32_t TILE>
 struct hub_geom {
     static constexpr uint32_t kBuckets = TILE / 2;
     static constexpr uint32_t kSlots = 4 * kBuckets;
     static constexpr int kBucketBits = __builtin_ctz(kBuckets);
     static constexpr int kFilterLog = __builtin_ctz(TILE) + 3;
-    static constexpr uint32_t kFilterShift = 32 - kFilterLog;
     static constexpr uint32_t kFilterBits = 1u << kFilterLog;
+    static constexpr uint32_t kWordShift = 32 - (kFilterLog - 5);   // position >> kWordShift: the filter word
     static_assert((TILE & (TILE - 1)) == 0 && TILE >= 256 && TILE <= 4096, "power-of-two tile");
     static_assert(kFilterBits / 32 >= (uint32_t)kHubB / 8, "filter words");
     // from a folded key
     __device__ static inline uint32_t bucket_of(uint32_t fold) { return mul24(fold, kHubBucketMul) >> (32 - kBucketBits); }
-    __device__ static inline uint32_t filter_bit_of(uint32_t fold) { return mul24(fold, kHubFilterMul) >> kFilterShift; }
+    // vertex w (< 2^23) of the member whose hub_member_mix is mix
+    __device__ static inline uint32_t filter_pos(uint32_t w, uint32_t mix) { return mul24(w, kHubFilterMul) + mix; }
 };
 
 // Buckets fill their slots in order, so a bucket whose last slot is empty
@@ -651,21 +657,21 @@ __device__ inline void hub_insert(uint32_t* hash, uint32_t e) {
 }
 
 // The whole bucket is read at once and its four slots compared without
-// branches (a vertex is stored at most once); the next bucket is read only
-// when this one is full and holds no match.  w is the key, fold its folded form.
+// branches; the next bucket is read only when this one is full and holds no
+// match.  key4 is the stored word with its direction bits cleared,
+// (m << 25) | (w << 2), and fold the folded key.  A slot XOR key4 is below 4
+// exactly when the slot holds the key (a key is stored at most once), and is
+// then the slot's direction bits: the smallest of the four, clamped to 4, is
+// the hit's direction bits, or 4 for no hit.
 template <uint32_t TILE>
-__device__ inline uint32_t hub_probe(const uint32_t* hash, uint32_t w, uint32_t fold) {
+__device__ inline uint32_t hub_probe(const uint32_t* hash, uint32_t key4, uint32_t fold) {
     using G = hub_geom<TILE>;
     const uint4* h4 = reinterpret_cast<const uint4*>(hash);
     uint32_t b = G::bucket_of(fold);
     for (;;) {
         const uint4 q = h4[b];
-        uint32_t r = kEmpty;
-        r = (q.x >> 2) == w ? q.x : r;
-        r = (q.y >> 2) == w ? q.y : r;
-        r = (q.z >> 2) == w ? q.z : r;
-        r = (q.w >> 2) == w ? q.w : r;
-        if (r != kEmpty || q.w == kEmpty) return r;
+        const uint32_t r = min(min(min(q.x ^ key4, q.y ^ key4), q.z ^ key4), min(q.w ^ key4, 4u));
+        if (r < 4u || q.w == kEmpty) return r;
         b = (b + 1) & (G::kBuckets - 1);
     }
 }
@@ -856,8 +862,8 @@ __device__ inline void hub_group_run(uint32_t js, uint32_t M, const dyad_rec* __
             while (m + 1 < M && eb[m + 1] <= f) ++m;
             const uint32_t v = nbr[S.tk[kTkHb + js + m] + (f - eb[m])];
             hub_insert<TILE>(S.hash, (m << 25) | v);
-            const uint32_t fb = G::filter_bit_of(hub_fold((m << 23) | (v >> 2)));
-            atomicOr(&S.filt[fb >> 5], 1u << (fb & 31u));
+            const uint32_t fp = G::filter_pos(v >> 2, hub_member_mix(m));
+            atomicOr(&S.filt[fp >> G::kWordShift], 1u << (fp & 31u));
         }
         if (multi_tile) {
             const uint32_t hb = S.tk[kTkHb + js], a = S.tk[kTkAnchor + js];
@@ -909,12 +915,12 @@ __device__ inline void hub_group_run(uint32_t js, uint32_t M, const dyad_rec* __
             if (lane < c) {
                 const uint32_t qe = ring_e[lane], qm = ring_m[lane];
                 const uint32_t w = qe >> 2, mm = qm >> 26;
-                const uint32_t hit = hub_probe<TILE>(S.hash, (mm << 23) | w, w + (mm << 20));
-                if (hit != kEmpty) {
+                const uint32_t fh = hub_probe<TILE>(S.hash, (qe & ~3u) | (mm << 25), w + (mm << 20));
+                if (fh < 4u) {
                     const uint32_t a = S.tk[kTkAnchor + js + mm];
                     const uint32_t x = (qm >> 3) & ((1u << 23) - 1u);
                     const uint32_t sx = (qm & 4u) ? 4u : 2u;
-                    const uint32_t code = (qm & 3u) | ((qe & 3u) << sx) | ((hit & 3u) << (6u - sx));
+                    const uint32_t code = (qm & 3u) | ((qe & 3u) << sx) | (fh << (6u - sx));
                     const uint32_t where = (w > a ? 1u : 0u) + (w > x ? 1u : 0u);
                     atomicAdd(&S.sig[code | (where << 6)], 1u);
                 }
@@ -933,6 +939,7 @@ __device__ inline void hub_group_run(uint32_t js, uint32_t M, const dyad_rec* __
                 }
             }
             uint32_t next = S.off[i + 1], p0 = S.pos[i], p1 = S.end[i], m = S.meta[i];
+            uint32_t mix = hub_member_mix(m >> 26);
             uint32_t bb = p0 / kHubGather - S.off[i];   // block of flattened index f: bb + f (mod 2^32)
             for (uint32_t win = q0; win < q1; win += 64u) {
                 // lanes past the quarter's end read its last block and keep no entry of it
@@ -955,6 +962,7 @@ __device__ inline void hub_group_run(uint32_t js, uint32_t M, const dyad_rec* __
                     p0 = S.pos[i];
                     p1 = S.end[i];
                     m = S.meta[i];
+                    mix = hub_member_mix(m >> 26);
                     bb = p0 / kHubGather - S.off[i];
                 }
                 const uint32_t b0 = (bb + f) * kHubGather;   // first entry of the block: b0 < p1, p0 < b0 + 8
@@ -964,25 +972,20 @@ __device__ inline void hub_group_run(uint32_t js, uint32_t M, const dyad_rec* __
                 const uint32_t klo = p0 > b0 ? p0 - b0 : 0u, khi = min(p1 - b0, kHubGather);
                 // bit k: word k is an entry of the row (none past the quarter's end)
                 const uint32_t vm = win + lane < q1 ? ((1u << khi) - 1u) & ~((1u << klo) - 1u) : 0u;
-                // Filter: the word of every entry first, then the bits, at
-                // bit (fold * C) >> kFilterShift of the folded key
-                // (e >> 2) + (m << 20) = (e + (m << 22)) >> 2.
-                const uint32_t m22 = (m >> 26) << 22;
-                uint32_t hk[kHubGather], fw[kHubGather], pm = 0;
+                // Filter: the word of every entry first, then the bits.
+                uint32_t fp[kHubGather], fw[kHubGather];
 #pragma unroll
                 for (uint32_t k = 0; k < kHubGather; ++k) {
-                    hk[k] = mul24((e[k] + m22) >> 2, kHubFilterMul) >> G::kFilterShift;
-                    fw[k] = S.filt[hk[k] >> 5];
+                    fp[k] = G::filter_pos(e[k] >> 2, mix);
+                    fw[k] = S.filt[fp[k] >> G::kWordShift];
                 }
-#pragma unroll
-                for (uint32_t k = 0; k < kHubGather; ++k) pm |= ((fw[k] >> (hk[k] & 31u)) & 1u) << k;
-                pm &= vm;
                 // appends: the entries that pass go to ring[cnt ..] in lane order
 #pragma unroll
                 for (uint32_t k = 0; k < kHubGather; ++k) {
-                    const bool pass = (pm >> k) & 1u;
-                    const unsigned long long bal = __ballot(pass);
-                    if (pass) {
+                    const bool pass = ((fw[k] >> (fp[k] & 31u)) & (vm >> k) & 1u) != 0u;
+                    const unsigned long long bal = __builtin_amdgcn_ballot_w64(pass);
+                    // (the lanes of the mask: the same lanes as pass, without a second compare)
+                    if (__builtin_amdgcn_inverse_ballot_w64(bal)) {
                         const uint32_t r = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
                                                                      __builtin_amdgcn_mbcnt_lo((uint32_t)bal, cnt));
                         ring_e[r] = e[k];

@@ -547,6 +547,8 @@ def main():
     ap.add_argument("--single-only", action="store_true",
                     help="default workload: leave out the batched and served legs")
     ap.add_argument("--tuning", default="", help="comma-separated key=value overrides, e.g. t_hub=256")
+    ap.add_argument("--shards", action="store_true",
+                    help="also time the census shards for 2, 4 and 8 GPUs' worth of work (extra launches)")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="also run 3 device-to-device copies of this many bytes (counter calibration)")
     args = ap.parse_args()
@@ -669,7 +671,8 @@ def main():
         bw = copy_bandwidth()
         line["roofline"]["copy_gbs"] = bw
         line["roofline"]["frac_of_copy"] = achieved / bw
-    line["shards"] = time_shards(ctx, g, counts, (2, 4, 8))
+    if args.shards:
+        line["shards"] = time_shards(ctx, g, counts, (2, 4, 8))
     gold = golden_counts("rmat", [g0]) if args.workload == "rmat" else None
     line["counts_equal_oracle"] = None if gold is None else line["counts"] == gold[0]
     g.release()

@@ -88,7 +88,7 @@ inline tc_tuning default_tuning(int cu_count) {
     t.lane_blocks = (uint32_t)cu * 8;
     t.wave_blocks = (uint32_t)cu * 10;
     t.group_blocks = (uint32_t)cu * 2;
-    t.batch_blocks = (uint32_t)cu * 6;   // six waves per SIMD: the batched kernel waits on memory
+    t.batch_blocks = (uint32_t)cu * 7;   // seven waves per SIMD: the batched kernel waits on memory
     t.hub_blocks = (uint32_t)cu * 8;
     t.tri = 1;      // whole-graph census through the triangles of the forward lists
     t.hub_tile = 1024;

@@ -1223,12 +1223,16 @@ __attribute__((amdgpu_waves_per_eu(hub_waves_per_simd<TILE>(), hub_waves_per_sim
     }
 }
 
+// Compiled for seven wavefronts per SIMD with 512-entry tiles (72 VGPRs; the
+// few values that no longer fit are reloaded once per item): the kernel waits
+// on memory, and more resident waves hide more of it than the spills cost.
+// Larger tiles are held to fewer waves by their LDS and keep their registers.
 template <int TW>
-__global__ __launch_bounds__(kBatchB) void k_census_batch(const graph_desc* __restrict__ G,
-                                                          const work_item* __restrict__ items,
-                                                          const uint32_t* __restrict__ num_items,
-                                                          unsigned long long* __restrict__ accs,
-                                                          unsigned int* __restrict__ ctr) {
+constexpr int batch_min_waves() { return TW <= 512 ? 7 : 1; }
+template <int TW>
+__global__ __launch_bounds__(kBatchB) __attribute__((amdgpu_waves_per_eu(batch_min_waves<TW>()))) void k_census_batch(
+    const graph_desc* __restrict__ G, const work_item* __restrict__ items, const uint32_t* __restrict__ num_items,
+    unsigned long long* __restrict__ accs, unsigned int* __restrict__ ctr) {
     static_assert(2 * kTotalsSlots * kBatchB <= batch_tile_words<TW>(), "per-lane slots fit in the tile area");
     __shared__ __attribute__((aligned(16))) uint32_t tiles[batch_tile_words<TW>()];
     __shared__ unsigned long long bins[wave_bins<kBatchB>::kWords];

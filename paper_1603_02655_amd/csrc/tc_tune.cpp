@@ -185,7 +185,7 @@ extern "C" int tc_autotune(tc_context ctx, const tc_graph* sample, int32_t count
         {&tc_tuning::lane_blocks, {cu * 4, cu * 8, cu * 16}, true, false},
         {&tc_tuning::wave_blocks, {cu * 5, cu * 10, cu * 20}, true, false},
         {&tc_tuning::group_blocks, {cu * 1, cu * 2, cu * 4}, true, false},
-        {&tc_tuning::batch_blocks, {cu * 2, cu * 4, cu * 6, cu * 8}, false, true},
+        {&tc_tuning::batch_blocks, {cu * 2, cu * 4, cu * 7, cu * 8}, false, true},
         {&tc_tuning::hub_blocks, {cu * 2, cu * 3, cu * 5, cu * 8}, true, true},
         {&tc_tuning::hub_tile, {512, 1024, 2048}, true, true},
         {&tc_tuning::wave_tile, {512, 1024, 2048}, true, false},

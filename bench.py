@@ -317,10 +317,16 @@ def run_serve(args) -> dict:
     from paper_1603_02655_amd import synth
     runs = []
     all_ok = True
-    for rate in [float(x) for x in str(args.rate).split(",")]:
+    plan = [(float(x), 0.0) for x in str(args.rate).split(",")]
+    if args.cold_frac > 0:
+        plan.append((float(args.cold_rate), float(args.cold_frac)))
+    for rate, cold_frac in plan:
         arrivals = synth.poisson_arrivals(rate, args.duration + 1.0, synth.rng_for(5, int(rate)))
         picks = rng.integers(0, len(hs), arrivals.size)
-        log(f"[bench] serving {arrivals.size} requests at {rate:.0f}/s for {args.duration + 1:.0f}s")
+        # cold requests carry the graph's arcs and are built inside their round
+        cold = rng.random(arrivals.size) < cold_frac
+        log(f"[bench] serving {arrivals.size} requests at {rate:.0f}/s for {args.duration + 1:.0f}s "
+            f"({cold.sum()} cold)")
         ctx.serve_reset_stats()
         sub_q = []
         lock = threading.Lock()
@@ -331,7 +337,11 @@ def run_serve(args) -> dict:
                 delay = arrivals[k] - (time.perf_counter() - t0)
                 if delay > 0:
                     time.sleep(delay)
-                tk = ctx.submit(hs[picks[k]])
+                if cold[k]:
+                    g = pool[picks[k]]
+                    tk = ctx.submit_arcs(g.n, g.src, g.dst)
+                else:
+                    tk = ctx.submit(hs[picks[k]])
                 with lock:
                     sub_q.append((tk, k, time.perf_counter()))
 
@@ -366,22 +376,31 @@ def run_serve(args) -> dict:
         all_ok &= ok
         meas = [i for i in range(arrivals.size) if arrivals[i] >= 1.0]
         ml = np.array([lat[i] for i in meas]) if meas else np.zeros(1)
-        runs.append({"rate": rate, "requests": int(arrivals.size), "measured": len(meas),
+        mc = np.array([lat[i] for i in meas if cold[i]])
+        mw = np.array([lat[i] for i in meas if not cold[i]])
+        runs.append({"rate": rate, "cold_fraction": cold_frac, "cold_requests": int(cold.sum()),
+                     "requests": int(arrivals.size), "measured": len(meas),
                      "wall_s": total_s, "completed_per_s": arrivals.size / total_s,
                      "offered_arcs_per_s": float(arcs[picks].mean() * rate),
                      "achieved_arcs_per_s": float(arcs[picks].sum() / total_s),
                      "p50_ms": float(np.percentile(ml, 50)), "p99_ms": float(np.percentile(ml, 99)),
                      "rounds": st["rounds"], "mean_admission_ms": st["mean_admission_ms"],
+                     "cold_p50_ms": float(np.percentile(mc, 50)) if mc.size else None,
+                     "cold_p99_ms": float(np.percentile(mc, 99)) if mc.size else None,
+                     "resident_p50_ms": float(np.percentile(mw, 50)) if mc.size and mw.size else None,
+                     "resident_p99_ms": float(np.percentile(mw, 99)) if mc.size and mw.size else None,
                      "results_equal_alone": ok})
         log(f"[bench] rate {rate}: {runs[-1]}")
+    warm = [r for r in runs if r["cold_fraction"] == 0.0] or runs
     res = {
         "workload": f"serving pool of {len(hs)} graphs (even ER, odd R-MAT r=0.10), n log-uniform "
                     "[1e3, 1e6], mean out-degree U[4,32]; Poisson arrivals",
         "duration_s": args.duration, "pool_arcs": int(arcs.sum()), "runs": runs,
         "per_graph_launches_rps": base_rps,
-        # at the first (nominal) rate: latency; at the last: what the loop sustains
+        # at the first (nominal) rate: latency; at the last resident-only rate:
+        # what the loop sustains
         "requests_per_s": runs[0]["completed_per_s"], "p50_ms": runs[0]["p50_ms"], "p99_ms": runs[0]["p99_ms"],
-        "capacity_rps": runs[-1]["completed_per_s"], "capacity_arcs_per_s": runs[-1]["achieved_arcs_per_s"],
+        "capacity_rps": warm[-1]["completed_per_s"], "capacity_arcs_per_s": warm[-1]["achieved_arcs_per_s"],
         "results_equal_alone": all_ok, "results_equal_oracle": equal_oracle,
     }
     for h in hs:
@@ -540,6 +559,9 @@ def main():
     ap.add_argument("--rate", default="2000,8000",
                     help="comma-separated arrival rates (requests/s); the last one measures capacity")
     ap.add_argument("--duration", type=float, default=5.0)
+    ap.add_argument("--cold-frac", type=float, default=0.05,
+                    help="fraction of cold requests (arcs submitted, built in their round) in one more serving run")
+    ap.add_argument("--cold-rate", type=float, default=1000.0, help="arrival rate of the run with cold requests")
     ap.add_argument("--pool", type=int, default=64)
     ap.add_argument("--batch-steps", type=int, default=10, help="timed batched launches")
     ap.add_argument("--autotune-sample", type=int, default=0,

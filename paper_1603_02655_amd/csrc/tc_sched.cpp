@@ -200,7 +200,12 @@ void scheduler::worker_main() {
         // 2. rounds past the watchdog: their jobs fail, the slot is retired
         for (size_t si = 0; si < slots_.size(); ++si) {
             slot_state& s = slots_[si];
-            if (!s.busy || s.finished.load() || t - s.t_launch <= lim_.watchdog_ms) continue;
+            if (!s.busy || s.finished.load()) continue;
+            if (!ex_->issued((int)si)) {
+                s.t_launch = t;   // still being prepared: the clock starts once it runs
+                continue;
+            }
+            if (t - s.t_launch <= lim_.watchdog_ms) continue;
             for (job* j : s.jobs) complete_locked(j, kErrDevice, t, retired);
             s.jobs.clear();
             s.busy = false;

@@ -87,6 +87,14 @@ struct round_executor {
     // Lock not held, when the worker stops: wait for the rounds of every slot
     // that was not abandoned.
     virtual void drain() = 0;
+    // Scheduler lock held, must not block: whether the round on `slot` has
+    // issued its device work.  An executor that prepares a round on a thread
+    // of its own (building graphs first) reports false until then; the
+    // watchdog measures a round from the first check at which this holds.
+    virtual bool issued(int slot) const {
+        (void)slot;
+        return true;
+    }
 };
 
 struct sched_stats {

@@ -12,8 +12,11 @@
 // never blocks.  A round that runs past the watchdog fails its tickets with
 // TC_ERR_DEVICE and its slot is not used again.
 #include <algorithm>
+#include <atomic>
+#include <condition_variable>
 #include <cstring>
 #include <memory>
+#include <thread>
 
 #include "tc_api_internal.h"
 #include "tc_sched.h"
@@ -111,16 +114,60 @@ uint64_t job_footprint(const serve_job& j) {
 }
 
 // The device side of the rounds: one stream and one set of staging buffers
-// per slot, the batched persistent kernels, a host callback per round.
+// per slot, the batched persistent kernels, a host callback per round.  A
+// round with requests to build goes to its slot's builder thread: a build
+// waits on the device several times, and the scheduler's thread keeps
+// launching rounds on the other slots meanwhile (the builds of different
+// slots overlap as well).
 class hip_executor : public sched::round_executor {
 public:
-    explicit hip_executor(tc_context_s* ctx) : ctx_(ctx) {}
+    explicit hip_executor(tc_context_s* ctx) : ctx_(ctx) {
+        for (int k = 0; k < kSlots; ++k) {
+            launched_[k].store(0);
+            issued_[k].store(0);
+        }
+    }
+    ~hip_executor() override { stop_builder(); }
     sched::scheduler* sched = nullptr;    // set before the first launch
     slot_buf slots[kSlots];
 
     int slot_count() const override { return kSlots; }
 
     int launch(int si, std::vector<sched::job*>& jobs) override {
+        bool cold = false;
+        for (sched::job* jb : jobs) cold = cold || static_cast<serve_job*>(jb)->cold;
+        if (!cold) return start_round(si, jobs, launched_[si].load());
+        std::lock_guard<std::mutex> lk(bmu_);
+        if (bstop_) return TC_ERR_SHUTDOWN;
+        if (!builder_[si].joinable()) builder_[si] = std::thread([this, si] { builder_main(si); });
+        const uint64_t gen = launched_[si].load() + 1;
+        launched_[si].store(gen);   // not issued until the builder issues it
+        pend_[si] = pending_round{gen, jobs};
+        has_[si] = true;            // (a slot holds one round at a time)
+        bcv_.notify_all();
+        return TC_OK;
+    }
+
+    // Rounds are numbered per slot; the builder marks a round issued once its
+    // work is on the stream (a late mark of an earlier round does not count).
+    bool issued(int si) const override { return issued_[si].load() == launched_[si].load(); }
+
+    // Ends the builder threads once their rounds are started.
+    void stop_builder() {
+        {
+            std::lock_guard<std::mutex> lk(bmu_);
+            bstop_ = true;
+        }
+        bcv_.notify_all();
+        for (std::thread& t : builder_)
+            if (t.joinable()) t.join();
+    }
+
+private:
+    // Builds the round's cold requests, uploads its items and starts the
+    // batched launch, the read-back and the completion callback on the
+    // slot's stream.  TC_OK: round_done(si) follows from the callback.
+    int start_round(int si, std::vector<sched::job*>& jobs, uint64_t gen) {
         slot_buf& s = slots[si];
         const tc_tuning tun = tuning_snapshot(ctx_);
         for (sched::job* jb : jobs) {
@@ -172,8 +219,40 @@ public:
             (void)hipStreamSynchronize(s.stream);
             return status_from_hip(e);
         }
+        issued_[si].store(gen);
         return TC_OK;
     }
+
+    struct pending_round {
+        uint64_t gen = 0;
+        std::vector<sched::job*> jobs;
+    };
+
+    void builder_main(int si) {
+        std::unique_lock<std::mutex> lk(bmu_);
+        for (;;) {
+            bcv_.wait(lk, [&] { return bstop_ || has_[si]; });
+            if (!has_[si]) return;   // stopping, nothing left
+            pending_round p = std::move(pend_[si]);
+            busy_[si] = true;
+            has_[si] = false;
+            lk.unlock();
+            const int rc = start_round(si, p.jobs, p.gen);
+            if (rc != TC_OK) {
+                // nothing runs (and the watchdog never timed the round, so its
+                // jobs are still the scheduler's): it completes now with rc
+                for (sched::job* j : p.jobs)
+                    if (j->status == TC_OK) j->status = rc;
+                issued_[si].store(p.gen);
+                sched->round_done(si);
+            }
+            lk.lock();
+            busy_[si] = false;
+            bcv_.notify_all();
+        }
+    }
+
+public:
 
     void collect(int si, std::vector<sched::job*>& jobs) override {
         for (size_t i = 0; i < jobs.size(); ++i) {
@@ -225,6 +304,14 @@ public:
     void abandon(int si) override { slots[si].dead = true; }
 
     void drain() override {
+        {
+            std::unique_lock<std::mutex> lk(bmu_);
+            bcv_.wait(lk, [&] {
+                for (int k = 0; k < kSlots; ++k)
+                    if (has_[k] || busy_[k]) return false;
+                return true;
+            });
+        }
         for (slot_buf& s : slots)
             if (!s.dead) (void)hipStreamSynchronize(s.stream);
     }
@@ -246,6 +333,14 @@ private:
     mutable std::mutex held_mu_;
     std::vector<device_graph> held_;
     uint64_t held_bytes_ = 0;
+    // builder threads, one per slot: the round with requests to build that
+    // the slot holds, if any
+    std::atomic<uint64_t> launched_[kSlots], issued_[kSlots];
+    std::mutex bmu_;
+    std::condition_variable bcv_;
+    pending_round pend_[kSlots];
+    bool has_[kSlots] = {}, busy_[kSlots] = {}, bstop_ = false;
+    std::thread builder_[kSlots];
 };
 
 }  // namespace
@@ -305,6 +400,7 @@ void serve_shutdown(tc_context_s* ctx) {
     serve_state* st = ctx->serve;
     if (!st) return;
     st->S->stop();
+    st->ex.stop_builder();
     // rounds the watchdog gave up on may still call back into the scheduler
     for (slot_buf& s : st->ex.slots)
         if (s.stream) (void)hipStreamSynchronize(s.stream);

@@ -42,6 +42,7 @@ struct fake_job : job {
     bool cold = false;         // holds `footprint` bytes after it ends, until release()
     bool hold = false;         // its round finishes only when the test lets it go
     bool hang = false;         // its round never finishes
+    double prepare_ms = 0;     // its round issues its work only after this long (a build first)
 };
 
 class fake_exec : public round_executor {
@@ -53,6 +54,9 @@ public:
 
     int slot_count() const override { return slots_; }
 
+    // a round being prepared has not issued its work yet
+    bool issued(int slot) const override { return now_ms() >= issue_at_[slot].load(); }
+
     int launch(int slot, std::vector<job*>& jobs) override {
         std::lock_guard<std::mutex> lk(mu_);
         ++launches_;
@@ -60,13 +64,14 @@ public:
         CHECK(!in_flight_[(size_t)slot]);   // never two rounds on one slot
         // admission invariant: what is admitted plus what is held fits the budget
         uint64_t fp = 0;
-        double delay = 0;
+        double delay = 0, prep = 0;
         bool hold = false, hang = false;
         for (job* jb : jobs) {
             fake_job* j = static_cast<fake_job*>(jb);
             CHECK(j->state == kRunning);
             fp += j->footprint;
             delay = std::max(delay, j->delay_ms);
+            prep = std::max(prep, j->prepare_ms);
             hold = hold || j->hold;
             hang = hang || j->hang;
             if (j->build_fails) j->status = -1;
@@ -79,8 +84,10 @@ public:
         }
         max_round_ = std::max<size_t>(max_round_, jobs.size());
         in_flight_[(size_t)slot] = fp + 1;
+        issue_at_[slot].store(now_ms() + prep);
         if (hang) return kOk;                 // round_done is never called
-        threads_.emplace_back([this, slot, delay, hold] {
+        threads_.emplace_back([this, slot, delay, hold, prep] {
+            sleep_ms(prep);
             if (hold) {
                 std::unique_lock<std::mutex> l2(hold_mu_);
                 hold_cv_.wait(l2, [this] { return released_; });
@@ -198,6 +205,7 @@ private:
     std::mutex hold_mu_;
     std::condition_variable hold_cv_;
     bool released_ = false;
+    std::atomic<double> issue_at_[16] = {};
 };
 
 struct harness {
@@ -370,6 +378,28 @@ static void scenario_watchdog() {
     std::printf("ok watchdog\n");
 }
 
+// A round still being prepared (its work not yet issued) is not timed by the
+// watchdog: a preparation far longer than the watchdog completes normally;
+// once a round has issued its work and then hangs, the watchdog drops it.
+static void scenario_watchdog_after_issue() {
+    harness h(2, 1ull << 30, 40.0);
+    fake_job* slow = mk(8, 10, 2.0);
+    slow->prepare_ms = 150.0;
+    const uint64_t ts = h.submit(slow);
+    uint64_t c[16];
+    CHECK(h.wait(ts, c) == kOk);
+    CHECK(h.S->stats().abandoned_rounds == 0);
+    fake_job* stuck = mk(9, 10);
+    stuck->prepare_ms = 100.0;
+    stuck->hang = true;
+    const double t0 = now_ms();
+    const uint64_t tk = h.submit(stuck);
+    CHECK(h.wait(tk, c) == kErrDevice);
+    CHECK(now_ms() - t0 >= 100.0 + 40.0 - 5.0);   // not before it issued its work plus the watchdog
+    CHECK(h.S->stats().abandoned_rounds == 1);
+    std::printf("ok watchdog after issue\n");
+}
+
 // While a graph has a job in flight its pending count is positive (the C API
 // returns TC_ERR_BUSY on release then); it drops to zero exactly when the
 // ticket is done.
@@ -484,6 +514,7 @@ int main() {
     scenario_launch_failure();
     scenario_build_error();
     scenario_watchdog();
+    scenario_watchdog_after_issue();
     scenario_busy_contract();
     scenario_stop();
     scenario_fifo();

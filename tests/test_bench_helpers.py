@@ -28,6 +28,18 @@ def test_source_hash_ignores_comments_and_whitespace(tmp_path, monkeypatch):
     assert ha == hb and ha != hc and len(ha) == 16
 
 
+def test_source_hash_skips_serving_and_tuner_sources(tmp_path, monkeypatch):
+    root = _fake_tree(tmp_path, "int f() { return 1; }\n")
+    monkeypatch.setattr(bench, "ROOT", str(root))
+    h0 = bench.census_source_hash()
+    csrc = root / "paper_1603_02655_amd" / "csrc"
+    for name in bench.NOT_CENSUS_SOURCES:
+        (csrc / name).write_text("int serve_something() { return 3; }\n")
+    assert bench.census_source_hash() == h0
+    (csrc / "tc_census.hip").write_text("int k() { return 4; }\n")
+    assert bench.census_source_hash() != h0
+
+
 def test_measured_traffic_only_for_the_current_sources(tmp_path, monkeypatch):
     root = _fake_tree(tmp_path, "int g() { return 0; }\n")
     monkeypatch.setattr(bench, "ROOT", str(root))

@@ -25,7 +25,7 @@ namespace tc {
 
 namespace {
 
-constexpr int kSlots = 3;                 // rounds in flight
+constexpr int kSlots = 4;                 // rounds in flight (HIP maps streams onto four hardware queues by default)
 constexpr size_t kMaxJobsPerRound = 512;
 // A round closes once its jobs hold this many neighbour entries (about 5 ms of
 // census at the batched rate): rounds stay short, so a request admitted behind

@@ -207,9 +207,14 @@ private:
                                    s.stream);
             if (e == hipSuccess)
                 e = hipMemcpyAsync(s.d_num, s.h_num, 2 * sizeof(uint32_t), hipMemcpyHostToDevice, s.stream);
+            // grids no larger than the round's items, so that small rounds
+            // leave the rest of the GPU to the rounds beside them
+            const uint32_t n_rest = (uint32_t)items.size() - n_hub;
+            const uint32_t grid = std::max<uint32_t>(1u, std::min<uint32_t>(tun.batch_blocks, n_rest));
+            const uint32_t hub_grid = std::max<uint32_t>(1u, std::min<uint32_t>(tun.hub_blocks, n_hub));
             if (e == hipSuccess)
                 e = batch_launch(s.d_desc, s.d_items, s.d_num, s.d_accs, (uint64_t)kNumClasses * jobs.size(),
-                                 s.d_ctr, tun.batch_blocks, tun.hub_blocks, tun.hub_tile, tun.batch_tile, s.stream);
+                                 s.d_ctr, grid, hub_grid, tun.hub_tile, tun.batch_tile, s.stream);
             if (e == hipSuccess)
                 e = hipMemcpyAsync(s.h_accs, s.d_accs, sizeof(unsigned long long) * kNumClasses * jobs.size(),
                                    hipMemcpyDeviceToHost, s.stream);

@@ -682,8 +682,8 @@ def main():
         "kernel_bytes": bytes_of,
         "step_ms": {"p10": float(np.percentile(step_ms, 10)), "p50": float(np.percentile(step_ms, 50)),
                     "p90": float(np.percentile(step_ms, 90))},
-        # the survey's per-dyad merge byte count, for reference only: the
-        # forward-list path never moves most of it
+        # the per-dyad merge's byte count (4 sum d^2 + 8p + 4(n+1)), for
+        # reference only: the forward-list path never moves most of it
         "merge_b_alg_gb": b_alg / 1e9,
         # every kernel of the step by its own byte model, over the whole step
         "step_roofline": {"bytes": step_bytes, "achieved": step_bytes / (el / args.steps) / 1e9,

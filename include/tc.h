@@ -271,7 +271,8 @@ int tc_poll(tc_context ctx, tc_ticket ticket, uint64_t counts[16], int* done);
 int tc_serve_stop(tc_context ctx);
 
 /* Watchdog of the serving loop: a round still running ms milliseconds after
- * its launch fails its tickets with TC_ERR_DEVICE, and its stream slot is not
+ * its device work was issued (for a round with graphs to build: after the
+ * builds) fails its tickets with TC_ERR_DEVICE, and its stream slot is not
  * used again (when every slot is lost, queued and new tickets fail with
  * TC_ERR_DEVICE).  Default 60000.  TC_ERR_ARG unless ms > 0. */
 int tc_serve_set_watchdog_ms(tc_context ctx, double ms);

@@ -76,6 +76,8 @@ graph_desc describe(const device_graph& g) {
     d.hub_groups = g.n_hub_groups;
     d.tri_tasks = g.tri.edges.n_tasks;
     d.tri_groups = g.tri.edges.n_groups;
+    d.hub_chunk = g.hub_chunk;
+    d.tri_chunk = g.tri.edges.chunk;
     return d;
 }
 

@@ -13,6 +13,7 @@ struct rec_set {
     hub_task* tasks = nullptr;
     uint32_t n_tasks = 0;
     uint32_t n_groups = 0;                    // groups of consecutive tasks (hub_task::group)
+    uint32_t chunk = kHubChunk;               // records per task and per group (kHubChunk or half)
     uint64_t off[kBuckets + 1] = {0, 0, 0, 0, 0};
     uint64_t cost[kBuckets] = {0, 0, 0, 0};   // sum of the two row lengths per bucket
     uint64_t stream = 0;                      // hub: sum of the non-anchor row lengths
@@ -49,6 +50,7 @@ struct device_graph {
     hub_task* hub_tasks = nullptr;
     uint32_t n_hub_tasks = 0;
     uint32_t n_hub_groups = 0;
+    uint32_t hub_chunk = kHubChunk;  // records per hub task and per group
     uint64_t bucket_off[kBuckets + 1] = {0, 0, 0, 0, 0};
     uint64_t bucket_cost[kBuckets] = {0, 0, 0, 0};   // sum of |N(u)|+|N(v)| per bucket
     uint64_t hub_stream = 0;   // sum over hub dyads of the non-anchor degree (entries probed)

@@ -466,12 +466,13 @@ __global__ __launch_bounds__(kT) void k_fwd_ptr(const int64_t* __restrict__ row_
 // classes this pass counts.
 __global__ __launch_bounds__(kT) void k_hub_ntasks(const unsigned int* __restrict__ hubcnt, int32_t n,
                                                     const int64_t* __restrict__ row_ptr, uint64_t* __restrict__ ntask,
-                                                    uint64_t big_row, int big, unsigned long long* __restrict__ counters) {
+                                                    uint64_t big_row, int big, uint32_t chunk,
+                                                    unsigned long long* __restrict__ counters) {
     int32_t h = (int32_t)(blockIdx.x * kT + threadIdx.x);
     unsigned long long staged = 0;
     if (h < n) {
         const uint64_t d = (uint64_t)(row_ptr[h + 1] - row_ptr[h]);
-        uint64_t t = (hubcnt[h] + kHubChunk - 1) / kHubChunk;
+        uint64_t t = (hubcnt[h] + chunk - 1) / chunk;
         if ((d > big_row) != (big != 0)) t = 0;
         ntask[h] = t;
         staged = t * (unsigned long long)d;
@@ -483,15 +484,16 @@ __global__ __launch_bounds__(kT) void k_hub_ntasks(const unsigned int* __restric
 __global__ __launch_bounds__(kT) void k_hub_emit(const unsigned int* __restrict__ hubcnt, int32_t n,
                                                   const int64_t* __restrict__ row_ptr, const uint64_t* __restrict__ rec_off,
                                                   const uint64_t* __restrict__ task_off, uint64_t task_base, uint64_t big_row,
-                                                  int big, uint64_t hub_begin, hub_task* __restrict__ tasks) {
+                                                  int big, uint32_t chunk, uint64_t hub_begin,
+                                                  hub_task* __restrict__ tasks) {
     int32_t h = (int32_t)(blockIdx.x * kT + threadIdx.x);
     if (h >= n) return;
     if (((uint64_t)(row_ptr[h + 1] - row_ptr[h]) > big_row) != (big != 0)) return;
     const uint64_t c = hubcnt[h], base = hub_begin + rec_off[h], t0 = task_base + task_off[h];
-    for (uint64_t j = 0; j * kHubChunk < c; ++j) {
+    for (uint64_t j = 0; j * chunk < c; ++j) {
         hub_task t;
-        t.begin = (uint32_t)(base + j * kHubChunk);
-        t.end = (uint32_t)(base + (c < (j + 1) * kHubChunk ? c : (j + 1) * kHubChunk));
+        t.begin = (uint32_t)(base + j * chunk);
+        t.end = (uint32_t)(base + (c < (j + 1) * chunk ? c : (j + 1) * chunk));
         t.anchor = (uint32_t)h;
         t.group = 0;
         tasks[t0 + j] = t;
@@ -500,13 +502,13 @@ __global__ __launch_bounds__(kT) void k_hub_emit(const unsigned int* __restrict_
 
 // Groups of consecutive hub tasks that one workgroup runs with a single LDS
 // tile: each window of kHubGroupTasks tasks is cut greedily before a task whose
-// records would take the group past kHubChunk or whose anchor row would take
+// records would take the group past `chunk` or whose anchor row would take
 // the group's rows past `tile` entries (a row longer than that stays alone).
 // Without goff, counts the groups of every window into gcount; with goff (the
 // scanned counts), stores the first task of each group in tasks[g].group.
 __global__ __launch_bounds__(kT) void k_hub_group(hub_task* __restrict__ tasks, const dyad_rec* __restrict__ recs,
                                                   uint64_t ntasks, const uint64_t* __restrict__ goff,
-                                                  uint64_t* __restrict__ gcount, uint32_t tile) {
+                                                  uint64_t* __restrict__ gcount, uint32_t tile, uint32_t chunk) {
     const uint64_t w = (uint64_t)blockIdx.x * kT + threadIdx.x;
     const uint64_t t0 = w * kHubGroupTasks;
     if (t0 >= ntasks) return;
@@ -517,7 +519,7 @@ __global__ __launch_bounds__(kT) void k_hub_group(hub_task* __restrict__ tasks, 
         const uint32_t b = tasks[t0 + j].begin, e = tasks[t0 + j].end, a = tasks[t0 + j].anchor;
         const dyad_rec r0 = recs[b];
         const uint32_t l = r0.u == a ? r0.eu - r0.bu : r0.ev - r0.bv, r = e - b;
-        if (j > gs && (l > tile || sr + r > kHubChunk || se + l > tile)) {
+        if (j > gs && (l > tile || sr + r > chunk || se + l > tile)) {
             starts[ng++] = gs;
             gs = j;
             sr = 0;
@@ -748,14 +750,15 @@ static hipError_t bucket_records(const uint32_t* nbr, const uint32_t* owner, con
                            out->recs);
         TRY(hipGetLastError());
     }
-    // hub tasks: runs of at most kHubChunk records per anchor
+    // hub tasks: runs of at most `chunk` records per anchor
+    out->chunk = out->off[kBucketHub + 1] - out->off[kBucketHub] >= kHubSplitRecords ? kHubChunk / 2 : kHubChunk;
     if (out->off[kBucketHub + 1] > out->off[kBucketHub] && n > 0) {
         TRY(hipMallocAsync((void**)&task_off, sizeof(uint64_t) * ((size_t)n + 1), s));
         // two passes: anchors with rows of several LDS tiles first, then the rest
         uint64_t part[2] = {0, 0};
         for (int big = 1; big >= 0; --big) {
             hipLaunchKernelGGL(k_hub_ntasks, dim3(grid1((uint64_t)n)), dim3(kT), 0, s, hubcnt, n, row_ptr, tmp64,
-                               (uint64_t)bp.hub_tile, big, counters);
+                               (uint64_t)bp.hub_tile, big, out->chunk, counters);
             TRY(hipGetLastError());
             TRY(scan_exclusive_u64(tmp64, task_off, (uint64_t)n, task_off + n, s));
             TRY(hipMemcpyAsync(&part[big], task_off + n, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
@@ -765,11 +768,11 @@ static hipError_t bucket_records(const uint32_t* nbr, const uint32_t* owner, con
         TRY(hipMalloc((void**)&out->tasks, sizeof(hub_task) * (ntasks ? ntasks : 1)));
         for (int big = 1; big >= 0; --big) {
             hipLaunchKernelGGL(k_hub_ntasks, dim3(grid1((uint64_t)n)), dim3(kT), 0, s, hubcnt, n, row_ptr, tmp64,
-                               (uint64_t)bp.hub_tile, big, (unsigned long long*)nullptr);
+                               (uint64_t)bp.hub_tile, big, out->chunk, (unsigned long long*)nullptr);
             TRY(hipGetLastError());
             TRY(scan_exclusive_u64(tmp64, task_off, (uint64_t)n, task_off + n, s));
             hipLaunchKernelGGL(k_hub_emit, dim3(grid1((uint64_t)n)), dim3(kT), 0, s, hubcnt, n, row_ptr, rec_off,
-                               task_off, big ? (uint64_t)0 : part[1], (uint64_t)bp.hub_tile, big,
+                               task_off, big ? (uint64_t)0 : part[1], (uint64_t)bp.hub_tile, big, out->chunk,
                                out->off[kBucketHub], out->tasks);
             TRY(hipGetLastError());
         }
@@ -780,13 +783,14 @@ static hipError_t bucket_records(const uint32_t* nbr, const uint32_t* owner, con
         uint64_t ngroups = 0;
         TRY(hipMallocAsync((void**)&gcount, sizeof(uint64_t) * (windows + 1), s));
         hipLaunchKernelGGL(k_hub_group, dim3(grid1(windows)), dim3(kT), 0, s, out->tasks,
-                           (const dyad_rec*)out->recs, ntasks, (const uint64_t*)nullptr, gcount, bp.hub_tile);
+                           (const dyad_rec*)out->recs, ntasks, (const uint64_t*)nullptr, gcount, bp.hub_tile,
+                           out->chunk);
         err = hipGetLastError();
         if (err == hipSuccess) err = scan_exclusive_u64(gcount, gcount, windows, gcount + windows, s);
         if (err == hipSuccess) {
             hipLaunchKernelGGL(k_hub_group, dim3(grid1(windows)), dim3(kT), 0, s, out->tasks,
                                (const dyad_rec*)out->recs, ntasks, (const uint64_t*)gcount, (uint64_t*)nullptr,
-                               bp.hub_tile);
+                               bp.hub_tile, out->chunk);
             err = hipGetLastError();
         }
         if (err == hipSuccess) err = hipMemcpyAsync(&ngroups, gcount + windows, sizeof(uint64_t), hipMemcpyDeviceToHost, s);
@@ -869,6 +873,7 @@ hipError_t bucket_dyads(device_graph* g, const bucket_params& bp, hipStream_t s)
     if (err != hipSuccess) return err;
     g->n_hub_tasks = d.n_tasks;
     g->n_hub_groups = d.n_groups;
+    g->hub_chunk = d.chunk;
     g->p = d.off[kBuckets];
     for (int b = 0; b <= kBuckets; ++b) g->bucket_off[b] = d.off[b];
     for (int b = 0; b < kBuckets; ++b) g->bucket_cost[b] = d.cost[b];

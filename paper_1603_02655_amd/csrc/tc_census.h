@@ -48,6 +48,7 @@ struct graph_desc {
     const uint4* rinfo;          // per row: bounds and prefix counts at its end
     uint32_t hub_ntasks, hub_groups;   // tasks and task groups over the dyad records
     uint32_t tri_tasks, tri_groups;    // tasks and task groups over the edge records
+    uint32_t hub_chunk, tri_chunk;     // records per hub task and per group, each view
 };
 // Item kinds: the mode (lane / wave / group / hub), with kItemTri when the item
 // indexes the forward-list edge records; kItemTotals covers neighbour entries

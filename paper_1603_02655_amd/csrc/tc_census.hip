@@ -680,8 +680,9 @@ __device__ inline uint32_t hub_probe(const uint32_t* hash, uint32_t key4, uint32
 // 4 * 256); a[count .. count + kScanPad) receive the total.  wsum holds 4 words
 // of LDS.
 constexpr uint32_t kScanPad = 8;
+template <uint32_t CH>
 __device__ inline void block_scan_u32(uint32_t* a, uint32_t count, uint32_t* wsum) {
-    constexpr uint32_t kPer = kHubChunk / kHubB;
+    constexpr uint32_t kPer = CH / kHubB;
     const uint32_t tid = threadIdx.x, lane = tid & 63u, wid = tid >> 6;
     uint32_t loc[kPer], s = 0;
 #pragma unroll
@@ -759,31 +760,34 @@ struct hub_lds {
 constexpr uint32_t kTkBegin = 0, kTkNrec = 8, kTkHb = 16, kTkLen = 24, kTkAnchor = 32, kTkGroups = 40,
                    kTkNGroups = 49, kTkRb = 50, kTkEb = 59, kHubTkWords = 68;
 static_assert(kHubGroupTasks == 8, "the task words hold eight tasks");
-template <uint32_t TILE>
+// CH: the records of a group the LDS holds (kHubChunk, or half of it for
+// graphs whose tasks and groups are half-size).
+template <uint32_t TILE, uint32_t CH>
 constexpr uint32_t hub_lds_words() {
-    return hub_geom<TILE>::kSlots + 2 * kHubRing * (kHubB / 64) + 3 * kHubChunk + (kHubChunk + kScanPad) + 4 + kSigs +
+    return hub_geom<TILE>::kSlots + 2 * kHubRing * (kHubB / 64) + 3 * CH + (CH + kScanPad) + 4 + kSigs +
            hub_geom<TILE>::kFilterBits / 32 + kHubTkWords;
 }
 
 // Wavefronts per SIMD the hub kernels are compiled for: seven (the best
 // measured with 1024-entry tiles), or as many workgroups as the LDS of a CU
 // (160 KiB) holds for larger tiles (the kernels' other LDS takes < 256 bytes).
-template <uint32_t TILE>
+template <uint32_t TILE, uint32_t CH>
 constexpr uint32_t hub_waves_per_simd() {
-    return (163840u / (4u * hub_lds_words<TILE>() + 256u)) < 7u ? (163840u / (4u * hub_lds_words<TILE>() + 256u)) : 7u;
+    return (163840u / (4u * hub_lds_words<TILE, CH>() + 256u)) < 7u ? (163840u / (4u * hub_lds_words<TILE, CH>() + 256u))
+                                                                   : 7u;
 }
 
-template <uint32_t TILE>
+template <uint32_t TILE, uint32_t CH>
 __device__ inline hub_lds hub_carve(uint32_t* base) {
     uint32_t* p = base;
     hub_lds S;
     S.hash = p;  p += hub_geom<TILE>::kSlots;
     S.ring_e = p;  p += kHubRing * (kHubB / 64);
     S.ring_m = p;  p += kHubRing * (kHubB / 64);
-    S.pos = p;   p += kHubChunk;
-    S.end = p;   p += kHubChunk;
-    S.meta = p;  p += kHubChunk;
-    S.off = p;   p += kHubChunk + kScanPad;
+    S.pos = p;   p += CH;
+    S.end = p;   p += CH;
+    S.meta = p;  p += CH;
+    S.off = p;   p += CH + kScanPad;
     S.wsum = p;  p += 4;
     S.sig = p;   p += kSigs;
     S.filt = p;  p += hub_geom<TILE>::kFilterBits / 32;
@@ -823,7 +827,7 @@ __device__ inline void hub_bins_flush(const hub_lds& S, const uint8_t* T, H& h) 
 // then each wavefront walks a quarter of the flattened block list, one block
 // per lane, and probes the entries that pass the tile's filter 64 at a time.
 // A hit adds one to the workgroup's count of the hit's signature.
-template <bool Tri, uint32_t TILE, class H>
+template <bool Tri, uint32_t TILE, uint32_t CH, class H>
 __device__ inline void hub_group_run(uint32_t js, uint32_t M, const dyad_rec* __restrict__ dyads,
                                      const uint32_t* __restrict__ nbr, const uint64_t* __restrict__ tpre, uint64_t n,
                                      uint32_t u_lo, uint32_t u_hi, const hub_lds& S, const uint8_t* T, H& h,
@@ -881,7 +885,7 @@ __device__ inline void hub_group_run(uint32_t js, uint32_t M, const dyad_rec* __
             }
         }
         __syncthreads();
-        block_scan_u32(S.off, nrec, S.wsum);
+        block_scan_u32<CH>(S.off, nrec, S.wsum);
         const uint32_t P = S.off[nrec];
         // The shared 32-bit signature counts grow by at most kHubGather * P in
         // this tile: they are flushed first when the tiles since the last flush
@@ -1020,13 +1024,14 @@ __device__ inline void hub_group_run(uint32_t js, uint32_t M, const dyad_rec* __
 
 // Hub tasks [t0, t1) (at most kHubGroupTasks) on the whole workgroup: their
 // descriptors and anchor rows are read once, and runs of consecutive tasks
-// whose records fit one chunk and whose anchor rows fit one tile are
-// processed together; a task whose anchor row spans several tiles runs alone.
-template <bool Tri, uint32_t TILE, class H>
+// whose records fit one chunk (`chunk` <= CH records, the graph's) and
+// whose anchor rows fit one tile are processed together; a task whose anchor
+// row spans several tiles runs alone.
+template <bool Tri, uint32_t TILE, uint32_t CH, class H>
 __device__ inline void hub_chunk_run(const hub_task* __restrict__ tasks, uint32_t t0, uint32_t t1,
                                      const dyad_rec* __restrict__ dyads, const uint32_t* __restrict__ nbr,
                                      const uint64_t* __restrict__ tpre, uint64_t n, uint32_t u_lo, uint32_t u_hi,
-                                     const hub_lds& S, const uint8_t* T, H& h, uint32_t& since) {
+                                     uint32_t chunk, const hub_lds& S, const uint8_t* T, H& h, uint32_t& since) {
     const uint32_t tid = threadIdx.x, nt = t1 - t0;
     if (tid < nt) {
         const hub_task tk = tasks[t0 + tid];
@@ -1045,7 +1050,7 @@ __device__ inline void hub_chunk_run(const hub_task* __restrict__ tasks, uint32_
         S.tk[kTkGroups] = 0;
         for (uint32_t j = 0; j < nt; ++j) {
             const uint32_t r = S.tk[kTkNrec + j], l = S.tk[kTkLen + j];
-            if (j > S.tk[kTkGroups + ng] && (l > TILE || sr + r > kHubChunk || se + l > TILE)) {
+            if (j > S.tk[kTkGroups + ng] && (l > TILE || sr + r > chunk || se + l > TILE)) {
                 S.tk[kTkGroups + ++ng] = j;
                 sr = 0;
                 se = 0;
@@ -1072,24 +1077,24 @@ __device__ inline void hub_chunk_run(const hub_task* __restrict__ tasks, uint32_
             S.tk[kTkEb + M] = e;
         }
         __syncthreads();
-        hub_group_run<Tri, TILE>(js, M, dyads, nbr, tpre, n, u_lo, u_hi, S, T, h, since);
+        hub_group_run<Tri, TILE, CH>(js, M, dyads, nbr, tpre, n, u_lo, u_hi, S, T, h, since);
         __syncthreads();
     }
 }
 
-template <bool Tri, uint32_t TILE>
+template <bool Tri, uint32_t TILE, uint32_t CH>
 __global__ __launch_bounds__(kHubB)
-__attribute__((amdgpu_waves_per_eu(hub_waves_per_simd<TILE>(), hub_waves_per_simd<TILE>()))) void k_census_hub(
+__attribute__((amdgpu_waves_per_eu(hub_waves_per_simd<TILE, CH>(), hub_waves_per_simd<TILE, CH>()))) void k_census_hub(
     census_args L, const hub_task* __restrict__ tasks, uint32_t ntasks, uint32_t ngroups, uint32_t g0, uint32_t g1,
     unsigned int* ctr) {
-    __shared__ __attribute__((aligned(16))) uint32_t hub_words[hub_lds_words<TILE>()];
+    __shared__ __attribute__((aligned(16))) uint32_t hub_words[hub_lds_words<TILE, CH>()];
     __shared__ unsigned long long bins[block_bins<kHubB>::kWords];
     __shared__ uint8_t T[64];
     __shared__ uint32_t s_next;
     if (threadIdx.x < 64) T[threadIdx.x] = L.table[threadIdx.x];
     block_bins<kHubB> h{bins};
     h.clear();
-    const hub_lds S = hub_carve<TILE>(hub_words);
+    const hub_lds S = hub_carve<TILE, CH>(hub_words);
     hub_bins_clear(S);
     __syncthreads();
     uint32_t since = 0;
@@ -1102,7 +1107,8 @@ __attribute__((amdgpu_waves_per_eu(hub_waves_per_simd<TILE>(), hub_waves_per_sim
     while (c < g1) {
         if (threadIdx.x == 0) s_next = g0 + take_chunk(ctr, xcd);
         const uint32_t t0 = tasks[c].group, t1 = c + 1 < ngroups ? tasks[c + 1].group : ntasks;
-        hub_chunk_run<Tri, TILE>(tasks, t0, t1, L.dyads, L.nbr, L.tpre, L.n, L.u_lo, L.u_hi, S, T, h, since);
+        hub_chunk_run<Tri, TILE, CH>(tasks, t0, t1, L.dyads, L.nbr, L.tpre, L.n, L.u_lo, L.u_hi, L.hub_chunk, S, T, h,
+                                 since);
         c = s_next;
         __syncthreads();
     }
@@ -1162,17 +1168,18 @@ __device__ inline void batch_item(uint32_t kind, const work_item& it, const grap
 
 template <uint32_t TILE>
 __global__ __launch_bounds__(kHubB)
-__attribute__((amdgpu_waves_per_eu(hub_waves_per_simd<TILE>(), hub_waves_per_simd<TILE>()))) void k_census_batch_hub(
+__attribute__((amdgpu_waves_per_eu(hub_waves_per_simd<TILE, kHubChunk>(), hub_waves_per_simd<TILE, kHubChunk>()))) void
+k_census_batch_hub(
     const graph_desc* __restrict__ G, const work_item* __restrict__ items, const uint32_t* __restrict__ nums,
     unsigned long long* __restrict__ accs, unsigned int* __restrict__ ctr) {
-    __shared__ __attribute__((aligned(16))) uint32_t hub_words[hub_lds_words<TILE>()];
+    __shared__ __attribute__((aligned(16))) uint32_t hub_words[hub_lds_words<TILE, kHubChunk>()];
     __shared__ unsigned long long bins[block_bins<kHubB>::kWords];
     __shared__ uint8_t T[64];
     __shared__ uint32_t s_next;
     if (threadIdx.x < 64) T[threadIdx.x] = c_table[threadIdx.x];
     block_bins<kHubB> h{bins};
     h.clear();
-    const hub_lds S = hub_carve<TILE>(hub_words);
+    const hub_lds S = hub_carve<TILE, kHubChunk>(hub_words);
     hub_bins_clear(S);
     __syncthreads();
     const uint32_t count = nums[0];
@@ -1204,12 +1211,14 @@ __attribute__((amdgpu_waves_per_eu(hub_waves_per_simd<TILE>(), hub_waves_per_sim
             if (cur_tri) {
                 const uint32_t t0 = g.edge_tasks[k].group;
                 const uint32_t t1 = k + 1 < g.tri_groups ? g.edge_tasks[k + 1].group : g.tri_tasks;
-                hub_chunk_run<true, TILE>(g.edge_tasks, t0, t1, g.edges, g.fwd, g.tpre, g.n, 0u, 0xffffffffu, S, T, h,
+                hub_chunk_run<true, TILE, kHubChunk>(g.edge_tasks, t0, t1, g.edges, g.fwd, g.tpre, g.n, 0u, 0xffffffffu,
+                                          g.tri_chunk, S, T, h,
                                           since);
             } else {
                 const uint32_t t0 = g.hub_tasks[k].group;
                 const uint32_t t1 = k + 1 < g.hub_groups ? g.hub_tasks[k + 1].group : g.hub_ntasks;
-                hub_chunk_run<false, TILE>(g.hub_tasks, t0, t1, g.dyads, g.nbr, g.tpre, g.n, 0u, 0xffffffffu, S, T, h,
+                hub_chunk_run<false, TILE, kHubChunk>(g.hub_tasks, t0, t1, g.dyads, g.nbr, g.tpre, g.n, 0u, 0xffffffffu,
+                                           g.hub_chunk, S, T, h,
                                            since);
             }
         }
@@ -1388,18 +1397,28 @@ void launch_bucket(int b, const census_args& L, uint64_t cnt, const census_confi
     }
 }
 
-// Task groups [g0, g1) of the ngroups.
+// Task groups [g0, g1) of the ngroups, on the instance whose LDS holds the
+// graph's groups (half-size groups: the smaller LDS).
+template <bool Tri, uint32_t CH>
+void launch_hub_ch(const census_args& L, const hub_task* tasks, uint32_t ntasks, uint32_t ngroups, uint32_t g0,
+                   uint32_t g1, const census_config& cfg, unsigned int* c, hipStream_t s) {
+    const dim3 grid((uint32_t)std::min<uint64_t>(g1 - g0, cfg.hub_blocks));
+    if (cfg.hub_tile == 512)
+        hipLaunchKernelGGL((k_census_hub<Tri, 512, CH>), grid, dim3(kHubB), 0, s, L, tasks, ntasks, ngroups, g0, g1, c);
+    else if (cfg.hub_tile == 1024)
+        hipLaunchKernelGGL((k_census_hub<Tri, 1024, CH>), grid, dim3(kHubB), 0, s, L, tasks, ntasks, ngroups, g0, g1, c);
+    else
+        hipLaunchKernelGGL((k_census_hub<Tri, 2048, CH>), grid, dim3(kHubB), 0, s, L, tasks, ntasks, ngroups, g0, g1, c);
+}
+
 template <bool Tri>
 void launch_hub(const census_args& L, const hub_task* tasks, uint32_t ntasks, uint32_t ngroups, uint32_t g0,
                 uint32_t g1, const census_config& cfg, unsigned int* counters, hipStream_t s) {
-    const dim3 grid((uint32_t)std::min<uint64_t>(g1 - g0, cfg.hub_blocks));
     unsigned int* c = counters + 3 * kXcds;
-    if (cfg.hub_tile == 512)
-        hipLaunchKernelGGL((k_census_hub<Tri, 512>), grid, dim3(kHubB), 0, s, L, tasks, ntasks, ngroups, g0, g1, c);
-    else if (cfg.hub_tile == 1024)
-        hipLaunchKernelGGL((k_census_hub<Tri, 1024>), grid, dim3(kHubB), 0, s, L, tasks, ntasks, ngroups, g0, g1, c);
+    if (L.hub_chunk <= kHubChunk / 2)
+        launch_hub_ch<Tri, kHubChunk / 2>(L, tasks, ntasks, ngroups, g0, g1, cfg, c, s);
     else
-        hipLaunchKernelGGL((k_census_hub<Tri, 2048>), grid, dim3(kHubB), 0, s, L, tasks, ntasks, ngroups, g0, g1, c);
+        launch_hub_ch<Tri, kHubChunk>(L, tasks, ntasks, ngroups, g0, g1, cfg, c, s);
 }
 
 }  // namespace
@@ -1449,7 +1468,7 @@ hipError_t census_launch(const device_graph& g, const census_slices& sl, bool tr
         if (ev) (void)hipEventRecord(ev[2 * b], bs);
         if (cnt > 0) {
             census_args L{recs + sl.begin[b], (uint32_t)cnt, nbr, g.tpre, (uint64_t)g.n, acc, sl.u_lo, sl.u_hi,
-                          table};
+                          table, tri ? g.tri.edges.chunk : g.hub_chunk};
             if (b == kBucketHub) {
                 L.dyads = recs;
                 if (tri) launch_hub<true>(L, tasks, ntasks, ngroups, hg0, hg1, cfg, counters, s);

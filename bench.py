@@ -129,13 +129,15 @@ def generate_pool(fn, count):
         return list(ex.map(fn, range(count), chunksize=max(1, count // (4 * workers))))
 
 
-def kernel_key(name: str, tri: bool, tuning: dict) -> str:
+def kernel_key(name: str, tri: bool, tuning: dict, chunk: int = 512) -> str:
     """The name rocprofv3 gives the template instance of a census kernel that
     runs with this tuning (namespace and arguments dropped), as used in the
-    tables under profiles/."""
+    tables under profiles/; `chunk`: the graph's records per hub task
+    (`tri_chunk` or `hub_chunk` of its info), which picks the hub kernel's
+    LDS instance."""
     t = "true" if tri else "false"
     if name == "k_census_hub":
-        return f"k_census_hub<{t}, {tuning['hub_tile']}u>"
+        return f"k_census_hub<{t}, {tuning['hub_tile']}u, {256 if chunk <= 256 else 512}u>"
     if name == "k_census_wave":
         return f"k_census_wave<{t}, {tuning['wave_tile']}>"
     if name == "k_census_group":
@@ -633,6 +635,7 @@ def main():
     #     row id and one prefix count (16 B), per row its bounds and the prefix
     #     count at its end (16 B).
     tri = bool(ctx.get_tuning()["tri"]) and info["fwd_entries"] > 0
+    chunk = info["tri_chunk"] if tri else info["hub_chunk"]
     if tri:
         cost, tasks = info["tri_bucket_cost"], info["tri_bucket_edges"]
         stream, staged = info["tri_stream"], info["tri_staged"]
@@ -672,11 +675,11 @@ def main():
                    "tuning": ctx.get_tuning()},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(args.workload, kernel_key(dom_name, tri, ctx.get_tuning())),
+                     "traffic": measured_traffic(args.workload, kernel_key(dom_name, tri, ctx.get_tuning(), chunk)),
                      "kernel": dom_name, "bytes_per_launch": bytes_dom, "kernel_ms": dom_ms,
                      "source_hash": census_source_hash(),
                      # what the counters say limits the kernel (SQ_ACTIVE_INST_VALU x 4 / SIMD cycles)
-                     "valu_busy": measured_valu_busy(args.workload, kernel_key(dom_name, tri, ctx.get_tuning()))},
+                     "valu_busy": measured_valu_busy(args.workload, kernel_key(dom_name, tri, ctx.get_tuning(), chunk))},
         "path": "forward-list triangles" if tri else "dyad intersections",
         "kernels_ms": per_launch_ms,
         "kernel_bytes": bytes_of,

@@ -80,6 +80,9 @@ typedef struct {
     /* groups of consecutive hub tasks that one workgroup stages into a single LDS tile */
     uint64_t hub_groups;          /* over the hub dyads */
     uint64_t tri_groups;          /* over the hub edges of the forward lists */
+    uint64_t hub_chunk;           /* records per hub task and per group, hub dyads (512, or 256 for
+                                     hub buckets of 2^20 records or more) */
+    uint64_t tri_chunk;           /* the same over the hub edges of the forward lists */
 } tc_graph_info;
 
 /* Degree-bucket thresholds and launch sizes.  A dyad one of whose endpoints

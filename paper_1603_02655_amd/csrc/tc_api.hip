@@ -86,6 +86,8 @@ void fill_info(const tc_graph_s* g, tc_graph_info* info) {
     info->tri_staged = t.edges.staged;
     info->hub_groups = g->g.n_hub_groups;
     info->tri_groups = t.edges.n_groups;
+    info->hub_chunk = g->g.hub_chunk;
+    info->tri_chunk = t.fwd_ptr ? t.edges.chunk : 0;
 }
 
 int run_census_locked(tc_context_s* ctx, const device_graph& g, const census_slices& sl,

@@ -60,7 +60,8 @@ class tc_graph_info(ctypes.Structure):
                 ("fwd_entries", ctypes.c_uint64), ("tri_bucket_edges", ctypes.c_uint64 * 4),
                 ("tri_bucket_cost", ctypes.c_uint64 * 4), ("tri_tasks", ctypes.c_uint64),
                 ("tri_stream", ctypes.c_uint64), ("tri_staged", ctypes.c_uint64),
-                ("hub_groups", ctypes.c_uint64), ("tri_groups", ctypes.c_uint64)]
+                ("hub_groups", ctypes.c_uint64), ("tri_groups", ctypes.c_uint64),
+                ("hub_chunk", ctypes.c_uint64), ("tri_chunk", ctypes.c_uint64)]
 
     def as_dict(self) -> dict:
         d = {k: getattr(self, k) for k, _ in self._fields_}

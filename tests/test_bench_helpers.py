@@ -82,7 +82,8 @@ def test_measured_valu_busy_only_for_the_current_sources(tmp_path, monkeypatch):
 
 def test_kernel_key_names_the_template_instance():
     t = {"hub_tile": 2048, "wave_tile": 512, "group_size": 512, "group_tile": 8192}
-    assert bench.kernel_key("k_census_hub", True, t) == "k_census_hub<true, 2048u>"
+    assert bench.kernel_key("k_census_hub", True, t) == "k_census_hub<true, 2048u, 512u>"
+    assert bench.kernel_key("k_census_hub", True, t, 256) == "k_census_hub<true, 2048u, 256u>"
     assert bench.kernel_key("k_census_wave", False, t) == "k_census_wave<false, 512>"
     assert bench.kernel_key("k_census_group", True, t) == "k_census_group<true, 512, 8192>"
     assert bench.kernel_key("k_census_lane", True, t) == "k_census_lane<true>"

@@ -25,6 +25,7 @@ struct batch_plan {
     hipGraphExec_t exec = nullptr;
     uint32_t grid = 0, hub_grid = 0;
     uint32_t hub_tile = 0, batch_tile = 0;  // LDS tiles the captured kernels use
+    uint32_t hub_chunk = 0;                 // largest records per hub task of the graphs (hub kernel instance)
     bool valid = false;                     // buffers describe `graphs`
     bool tri = false;                       // ... through their forward lists
 
@@ -110,9 +111,9 @@ void append_items(const device_graph& g, uint32_t gi, bool tri, std::vector<work
 namespace {
 
 hipError_t ensure_capacity(batch_plan* p, uint32_t graphs, uint32_t items, hipStream_t s, uint32_t grid,
-                           uint32_t hub_grid, uint32_t hub_tile, uint32_t batch_tile) {
+                           uint32_t hub_grid, uint32_t hub_tile, uint32_t batch_tile, uint32_t hub_chunk) {
     if (p->exec && graphs <= p->cap_graphs && items <= p->cap_items && grid == p->grid && hub_grid == p->hub_grid &&
-        hub_tile == p->hub_tile && batch_tile == p->batch_tile)
+        hub_tile == p->hub_tile && batch_tile == p->batch_tile && hub_chunk == p->hub_chunk)
         return hipSuccess;
     (void)hipStreamSynchronize(s);
     p->release();
@@ -122,6 +123,7 @@ hipError_t ensure_capacity(batch_plan* p, uint32_t graphs, uint32_t items, hipSt
     p->hub_grid = hub_grid;
     p->hub_tile = hub_tile;
     p->batch_tile = batch_tile;
+    p->hub_chunk = hub_chunk;
     hipError_t e = hipMalloc((void**)&p->d_desc, sizeof(graph_desc) * p->cap_graphs);
     if (e == hipSuccess) e = hipMalloc((void**)&p->d_items, sizeof(work_item) * p->cap_items);
     if (e == hipSuccess) e = hipMalloc((void**)&p->d_num, 2 * sizeof(uint32_t));
@@ -137,7 +139,7 @@ hipError_t ensure_capacity(batch_plan* p, uint32_t graphs, uint32_t items, hipSt
     e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return e;
     hipError_t el = batch_launch(p->d_desc, p->d_items, p->d_num, p->d_accs, (uint64_t)kNumClasses * p->cap_graphs,
-                                 p->d_ctr, p->grid, p->hub_grid, p->hub_tile, p->batch_tile, s);
+                                 p->d_ctr, p->grid, p->hub_grid, p->hub_tile, p->batch_tile, p->hub_chunk, s);
     hipError_t ec = hipMemcpyAsync(p->h_accs, p->d_accs, sizeof(unsigned long long) * kNumClasses * p->cap_graphs,
                                    hipMemcpyDeviceToHost, s);
     e = hipStreamEndCapture(s, &p->graph);
@@ -172,15 +174,17 @@ extern "C" int tc_census_batch(tc_context ctx, const tc_graph* graphs, int32_t c
           p->batch_tile == ctx->tuning.batch_tile && p->tri == tri)) {
         std::vector<work_item> items, rest;
         std::vector<graph_desc> descs(count);
+        uint32_t hub_chunk = 0;
         for (int32_t i = 0; i < count; ++i) {
             const device_graph& g = graphs[i]->g;
             descs[i] = describe(g);
             append_items(g, (uint32_t)i, tri && g.tri.fwd_ptr, items, rest);
+            hub_chunk = std::max(hub_chunk, tri && g.tri.fwd_ptr ? g.tri.edges.chunk : g.hub_chunk);
         }
         const uint32_t nums[2] = {(uint32_t)items.size(), (uint32_t)(items.size() + rest.size())};
         items.insert(items.end(), rest.begin(), rest.end());     // hub items first
         e = ensure_capacity(p, (uint32_t)count, (uint32_t)items.size(), ctx->stream, ctx->tuning.batch_blocks,
-                            ctx->tuning.hub_blocks, ctx->tuning.hub_tile, ctx->tuning.batch_tile);
+                            ctx->tuning.hub_blocks, ctx->tuning.hub_tile, ctx->tuning.batch_tile, hub_chunk);
         if (e != hipSuccess) return status_from_hip(e);
         uint32_t nitems = (uint32_t)items.size();
         e = hipMemcpyAsync(p->d_desc, descs.data(), sizeof(graph_desc) * count, hipMemcpyHostToDevice, ctx->stream);

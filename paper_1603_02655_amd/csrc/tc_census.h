@@ -67,10 +67,13 @@ constexpr uint32_t kBatchWavePerItem = 16;    // four wavefronts, four dyads eac
 // items items[0..nums[0]) with hub_grid workgroups, and the batch kernel
 // (wave-mode tile batch_tile, group-mode tile 4 x batch_tile) over the other
 // items items[nums[0]..nums[1]) with `grid` workgroups (nums: 2 words of
-// device memory).  hipErrorInvalidValue for a tile the kernels are not built for.
+// device memory).  hub_chunk: the largest records per hub task of the graphs
+// (a launch of graphs with half-size tasks only runs the hub kernel instance
+// with the smaller LDS).  hipErrorInvalidValue for a tile the kernels are not
+// built for.
 hipError_t batch_launch(const graph_desc* descs, const work_item* items, const uint32_t* nums,
                         unsigned long long* accs, uint64_t acc_words, unsigned int* counters, uint32_t grid,
-                        uint32_t hub_grid, uint32_t hub_tile, uint32_t batch_tile, hipStream_t s);
+                        uint32_t hub_grid, uint32_t hub_tile, uint32_t batch_tile, uint32_t hub_chunk, hipStream_t s);
 
 // Copies the 16-class table into the constant table the batch kernel reads.
 hipError_t census_upload_table();

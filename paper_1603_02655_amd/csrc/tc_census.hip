@@ -1166,20 +1166,20 @@ __device__ inline void batch_item(uint32_t kind, const work_item& it, const grap
     }
 }
 
-template <uint32_t TILE>
+template <uint32_t TILE, uint32_t CH>
 __global__ __launch_bounds__(kHubB)
-__attribute__((amdgpu_waves_per_eu(hub_waves_per_simd<TILE, kHubChunk>(), hub_waves_per_simd<TILE, kHubChunk>()))) void
+__attribute__((amdgpu_waves_per_eu(hub_waves_per_simd<TILE, CH>(), hub_waves_per_simd<TILE, CH>()))) void
 k_census_batch_hub(
     const graph_desc* __restrict__ G, const work_item* __restrict__ items, const uint32_t* __restrict__ nums,
     unsigned long long* __restrict__ accs, unsigned int* __restrict__ ctr) {
-    __shared__ __attribute__((aligned(16))) uint32_t hub_words[hub_lds_words<TILE, kHubChunk>()];
+    __shared__ __attribute__((aligned(16))) uint32_t hub_words[hub_lds_words<TILE, CH>()];
     __shared__ unsigned long long bins[block_bins<kHubB>::kWords];
     __shared__ uint8_t T[64];
     __shared__ uint32_t s_next;
     if (threadIdx.x < 64) T[threadIdx.x] = c_table[threadIdx.x];
     block_bins<kHubB> h{bins};
     h.clear();
-    const hub_lds S = hub_carve<TILE, kHubChunk>(hub_words);
+    const hub_lds S = hub_carve<TILE, CH>(hub_words);
     hub_bins_clear(S);
     __syncthreads();
     const uint32_t count = nums[0];
@@ -1211,13 +1211,13 @@ k_census_batch_hub(
             if (cur_tri) {
                 const uint32_t t0 = g.edge_tasks[k].group;
                 const uint32_t t1 = k + 1 < g.tri_groups ? g.edge_tasks[k + 1].group : g.tri_tasks;
-                hub_chunk_run<true, TILE, kHubChunk>(g.edge_tasks, t0, t1, g.edges, g.fwd, g.tpre, g.n, 0u, 0xffffffffu,
+                hub_chunk_run<true, TILE, CH>(g.edge_tasks, t0, t1, g.edges, g.fwd, g.tpre, g.n, 0u, 0xffffffffu,
                                           g.tri_chunk, S, T, h,
                                           since);
             } else {
                 const uint32_t t0 = g.hub_tasks[k].group;
                 const uint32_t t1 = k + 1 < g.hub_groups ? g.hub_tasks[k + 1].group : g.hub_ntasks;
-                hub_chunk_run<false, TILE, kHubChunk>(g.hub_tasks, t0, t1, g.dyads, g.nbr, g.tpre, g.n, 0u, 0xffffffffu,
+                hub_chunk_run<false, TILE, CH>(g.hub_tasks, t0, t1, g.dyads, g.nbr, g.tpre, g.n, 0u, 0xffffffffu,
                                            g.hub_chunk, S, T, h,
                                            since);
             }
@@ -1332,9 +1332,13 @@ namespace {
 template <uint32_t HT, int BT>
 void launch_batch_kernels(const graph_desc* descs, const work_item* items, const uint32_t* nums,
                           unsigned long long* accs, unsigned int* counters, uint32_t grid, uint32_t hub_grid,
-                          hipStream_t s) {
-    hipLaunchKernelGGL(k_census_batch_hub<HT>, dim3(hub_grid), dim3(kHubB), 0, s, descs, items, nums, accs,
-                       counters);
+                          uint32_t hub_chunk, hipStream_t s) {
+    if (hub_chunk <= kHubChunk / 2)
+        hipLaunchKernelGGL((k_census_batch_hub<HT, kHubChunk / 2>), dim3(hub_grid), dim3(kHubB), 0, s, descs, items,
+                           nums, accs, counters);
+    else
+        hipLaunchKernelGGL((k_census_batch_hub<HT, kHubChunk>), dim3(hub_grid), dim3(kHubB), 0, s, descs, items, nums,
+                           accs, counters);
     hipLaunchKernelGGL(k_census_batch<BT>, dim3(grid), dim3(kBatchB), 0, s, descs, items, nums, accs,
                        counters + kXcds);
 }
@@ -1342,24 +1346,27 @@ void launch_batch_kernels(const graph_desc* descs, const work_item* items, const
 template <uint32_t HT>
 void launch_batch_bt(uint32_t bt, const graph_desc* descs, const work_item* items, const uint32_t* nums,
                      unsigned long long* accs, unsigned int* counters, uint32_t grid, uint32_t hub_grid,
-                     hipStream_t s) {
-    if (bt == 512) launch_batch_kernels<HT, 512>(descs, items, nums, accs, counters, grid, hub_grid, s);
-    else if (bt == 1024) launch_batch_kernels<HT, 1024>(descs, items, nums, accs, counters, grid, hub_grid, s);
-    else launch_batch_kernels<HT, 2048>(descs, items, nums, accs, counters, grid, hub_grid, s);
+                     uint32_t hub_chunk, hipStream_t s) {
+    if (bt == 512) launch_batch_kernels<HT, 512>(descs, items, nums, accs, counters, grid, hub_grid, hub_chunk, s);
+    else if (bt == 1024)
+        launch_batch_kernels<HT, 1024>(descs, items, nums, accs, counters, grid, hub_grid, hub_chunk, s);
+    else launch_batch_kernels<HT, 2048>(descs, items, nums, accs, counters, grid, hub_grid, hub_chunk, s);
 }
 
 }  // namespace
 
 hipError_t batch_launch(const graph_desc* descs, const work_item* items, const uint32_t* nums,
                         unsigned long long* accs, uint64_t acc_words, unsigned int* counters, uint32_t grid,
-                        uint32_t hub_grid, uint32_t hub_tile, uint32_t batch_tile, hipStream_t s) {
+                        uint32_t hub_grid, uint32_t hub_tile, uint32_t batch_tile, uint32_t hub_chunk, hipStream_t s) {
     if (!tile_supported(hub_tile, 1024, 4096, 256, batch_tile)) return hipErrorInvalidValue;
     uint32_t zb = (uint32_t)std::min<uint64_t>((acc_words + 255) / 256, 1024);
     hipLaunchKernelGGL(k_fill_u64_grid, dim3(zb ? zb : 1), dim3(256), 0, s, accs, acc_words);
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, counters, 2 * kXcds);
-    if (hub_tile == 512) launch_batch_bt<512>(batch_tile, descs, items, nums, accs, counters, grid, hub_grid, s);
-    else if (hub_tile == 1024) launch_batch_bt<1024>(batch_tile, descs, items, nums, accs, counters, grid, hub_grid, s);
-    else launch_batch_bt<2048>(batch_tile, descs, items, nums, accs, counters, grid, hub_grid, s);
+    if (hub_tile == 512)
+        launch_batch_bt<512>(batch_tile, descs, items, nums, accs, counters, grid, hub_grid, hub_chunk, s);
+    else if (hub_tile == 1024)
+        launch_batch_bt<1024>(batch_tile, descs, items, nums, accs, counters, grid, hub_grid, hub_chunk, s);
+    else launch_batch_bt<2048>(batch_tile, descs, items, nums, accs, counters, grid, hub_grid, hub_chunk, s);
     return hipGetLastError();
 }
 

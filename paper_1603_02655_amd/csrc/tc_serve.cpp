@@ -182,6 +182,7 @@ private:
         }
         std::vector<work_item> items, rest;
         std::vector<graph_desc> descs(jobs.size());
+        uint32_t hub_chunk = 0;
         for (size_t i = 0; i < jobs.size(); ++i) {
             serve_job* j = static_cast<serve_job*>(jobs[i]);
             if (j->status != TC_OK) {
@@ -190,7 +191,9 @@ private:
             }
             const device_graph& g = j->cold ? j->built : j->g->g;
             descs[i] = describe(g);
-            append_items(g, (uint32_t)i, tun.tri && g.tri.fwd_ptr, items, rest);
+            const bool tri = tun.tri && g.tri.fwd_ptr;
+            append_items(g, (uint32_t)i, tri, items, rest);
+            hub_chunk = std::max(hub_chunk, tri ? g.tri.edges.chunk : g.hub_chunk);
         }
         const uint32_t n_hub = (uint32_t)items.size();
         items.insert(items.end(), rest.begin(), rest.end());     // hub items first
@@ -214,7 +217,7 @@ private:
             const uint32_t hub_grid = std::max<uint32_t>(1u, std::min<uint32_t>(tun.hub_blocks, n_hub));
             if (e == hipSuccess)
                 e = batch_launch(s.d_desc, s.d_items, s.d_num, s.d_accs, (uint64_t)kNumClasses * jobs.size(),
-                                 s.d_ctr, grid, hub_grid, tun.hub_tile, tun.batch_tile, s.stream);
+                                 s.d_ctr, grid, hub_grid, tun.hub_tile, tun.batch_tile, hub_chunk, s.stream);
             if (e == hipSuccess)
                 e = hipMemcpyAsync(s.h_accs, s.d_accs, sizeof(unsigned long long) * kNumClasses * jobs.size(),
                                    hipMemcpyDeviceToHost, s.stream);

@@ -80,9 +80,10 @@ typedef struct {
     /* groups of consecutive hub tasks that one workgroup stages into a single LDS tile */
     uint64_t hub_groups;          /* over the hub dyads */
     uint64_t tri_groups;          /* over the hub edges of the forward lists */
-    uint64_t hub_chunk;           /* records per hub task and per group, hub dyads (512, or 256 for
-                                     hub buckets of 2^20 records or more) */
-    uint64_t tri_chunk;           /* the same over the hub edges of the forward lists */
+    uint64_t hub_chunk;           /* records per hub task and per group, hub dyads (512) */
+    uint64_t tri_chunk;           /* the same over the hub edges of the forward lists as tc_census runs
+                                     them: 256 for hub buckets of 2^20 edges or more (batched launches
+                                     run a second set of 512-record tasks), else 512 */
 } tc_graph_info;
 
 /* Degree-bucket thresholds and launch sizes.  A dyad one of whose endpoints

@@ -81,13 +81,15 @@ void fill_info(const tc_graph_s* g, tc_graph_info* info) {
         info->tri_bucket_edges[b] = t.edges.off[b + 1] - t.edges.off[b];
         info->tri_bucket_cost[b] = t.edges.cost[b];
     }
-    info->tri_tasks = t.edges.n_tasks;
+    // the forward lists' hub tasks a census runs: the half-size set when there is one
+    const bool fine = t.edges.fine_tasks != nullptr;
+    info->tri_tasks = fine ? t.edges.fine_n_tasks : t.edges.n_tasks;
     info->tri_stream = t.edges.stream;
-    info->tri_staged = t.edges.staged;
+    info->tri_staged = fine ? t.edges.fine_staged : t.edges.staged;
     info->hub_groups = g->g.n_hub_groups;
-    info->tri_groups = t.edges.n_groups;
+    info->tri_groups = fine ? t.edges.fine_n_groups : t.edges.n_groups;
     info->hub_chunk = g->g.hub_chunk;
-    info->tri_chunk = t.fwd_ptr ? t.edges.chunk : 0;
+    info->tri_chunk = !t.fwd_ptr ? 0 : fine ? kHubChunk / 2 : t.edges.chunk;
 }
 
 int run_census_locked(tc_context_s* ctx, const device_graph& g, const census_slices& sl,
@@ -469,7 +471,8 @@ int tc_census_shard(tc_context ctx, tc_graph g, int32_t shard, int32_t nshards, 
             sl.begin[b] = lo + len * k / G;
             sl.end[b] = lo + len * (k + 1) / G;
         }
-        const uint64_t ng = tri ? dg.tri.edges.n_groups : dg.n_hub_groups;
+        const uint64_t ng = !tri ? dg.n_hub_groups
+                            : dg.tri.edges.fine_tasks ? dg.tri.edges.fine_n_groups : dg.tri.edges.n_groups;
         sl.hub_g0 = (uint32_t)(ng * k / G);
         sl.hub_g1 = (uint32_t)(ng * (k + 1) / G);
         sl.totals_begin = dg.U * k / G;

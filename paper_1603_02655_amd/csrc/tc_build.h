@@ -13,11 +13,18 @@ struct rec_set {
     hub_task* tasks = nullptr;
     uint32_t n_tasks = 0;
     uint32_t n_groups = 0;                    // groups of consecutive tasks (hub_task::group)
-    uint32_t chunk = kHubChunk;               // records per task and per group (kHubChunk or half)
+    uint32_t chunk = kHubChunk;               // records per task and per group
+    // A second set of tasks and groups of kHubChunk / 2 records over the same
+    // records (forward-list hub buckets of kHubSplitRecords records or more):
+    // the set a single-graph census runs, on the hub kernel with the smaller LDS.
+    hub_task* fine_tasks = nullptr;
+    uint32_t fine_n_tasks = 0;
+    uint32_t fine_n_groups = 0;
     uint64_t off[kBuckets + 1] = {0, 0, 0, 0, 0};
     uint64_t cost[kBuckets] = {0, 0, 0, 0};   // sum of the two row lengths per bucket
     uint64_t stream = 0;                      // hub: sum of the non-anchor row lengths
     uint64_t staged = 0;                      // hub: sum over tasks of the anchor row length
+    uint64_t fine_staged = 0;                 // ... over the tasks of the second set
 };
 
 // Degree order: x precedes y when (|N(x)|, x) < (|N(y)|, y).  The forward list

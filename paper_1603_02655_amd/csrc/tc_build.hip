@@ -697,6 +697,60 @@ done:
     return st;
 }
 
+// Cuts the hub records of each anchor (contiguous from hub_begin + rec_off[h])
+// into tasks of at most `chunk` records, anchors whose rows span several LDS
+// tiles first, and the tasks into groups (k_hub_group).  The staged entries
+// of the tasks are added to ctr[13] unless ctr is null.
+static hipError_t cut_hub_tasks(const unsigned int* hubcnt, int32_t n, const int64_t* row_ptr,
+                                const uint64_t* rec_off, uint64_t* tmp64, uint64_t hub_begin, const dyad_rec* recs,
+                                const bucket_params& bp, uint32_t chunk, unsigned long long* ctr, hipStream_t s,
+                                hub_task** tasks_out, uint32_t* ntasks_out, uint32_t* ngroups_out) {
+    hipError_t err = hipSuccess;
+    uint64_t *task_off = nullptr, *gcount = nullptr;
+    hub_task* tasks = nullptr;
+    uint64_t part[2] = {0, 0}, ntasks = 0, ngroups = 0, windows = 0;
+    TRY(hipMallocAsync((void**)&task_off, sizeof(uint64_t) * ((size_t)n + 1), s));
+    for (int big = 1; big >= 0; --big) {
+        hipLaunchKernelGGL(k_hub_ntasks, dim3(grid1((uint64_t)n)), dim3(kT), 0, s, hubcnt, n, row_ptr, tmp64,
+                           (uint64_t)bp.hub_tile, big, chunk, ctr);
+        TRY(hipGetLastError());
+        TRY(scan_exclusive_u64(tmp64, task_off, (uint64_t)n, task_off + n, s));
+        TRY(hipMemcpyAsync(&part[big], task_off + n, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+        TRY(hipStreamSynchronize(s));
+    }
+    ntasks = part[1] + part[0];
+    TRY(hipMalloc((void**)&tasks, sizeof(hub_task) * (ntasks ? ntasks : 1)));
+    for (int big = 1; big >= 0; --big) {
+        hipLaunchKernelGGL(k_hub_ntasks, dim3(grid1((uint64_t)n)), dim3(kT), 0, s, hubcnt, n, row_ptr, tmp64,
+                           (uint64_t)bp.hub_tile, big, chunk, (unsigned long long*)nullptr);
+        TRY(hipGetLastError());
+        TRY(scan_exclusive_u64(tmp64, task_off, (uint64_t)n, task_off + n, s));
+        hipLaunchKernelGGL(k_hub_emit, dim3(grid1((uint64_t)n)), dim3(kT), 0, s, hubcnt, n, row_ptr, rec_off, task_off,
+                           big ? (uint64_t)0 : part[1], (uint64_t)bp.hub_tile, big, chunk, hub_begin, tasks);
+        TRY(hipGetLastError());
+    }
+    windows = (ntasks + kHubGroupTasks - 1) / kHubGroupTasks;
+    TRY(hipMallocAsync((void**)&gcount, sizeof(uint64_t) * (windows + 1), s));
+    hipLaunchKernelGGL(k_hub_group, dim3(grid1(windows)), dim3(kT), 0, s, tasks, recs, ntasks,
+                       (const uint64_t*)nullptr, gcount, bp.hub_tile, chunk);
+    TRY(hipGetLastError());
+    TRY(scan_exclusive_u64(gcount, gcount, windows, gcount + windows, s));
+    hipLaunchKernelGGL(k_hub_group, dim3(grid1(windows)), dim3(kT), 0, s, tasks, recs, ntasks,
+                       (const uint64_t*)gcount, (uint64_t*)nullptr, bp.hub_tile, chunk);
+    TRY(hipGetLastError());
+    TRY(hipMemcpyAsync(&ngroups, gcount + windows, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+    TRY(hipStreamSynchronize(s));
+    *tasks_out = tasks;
+    tasks = nullptr;
+    *ntasks_out = (uint32_t)ntasks;
+    *ngroups_out = (uint32_t)ngroups;
+done:
+    if (tasks) (void)hipFree(tasks);
+    if (task_off) (void)hipFreeAsync(task_off, s);
+    if (gcount) (void)hipFreeAsync(gcount, s);
+    return err;
+}
+
 // Buckets the entries of one adjacency view (nbr / owner / row_ptr over U
 // entries and n rows) into `out`: records, hub tasks and the per-bucket sums.
 static hipError_t bucket_records(const uint32_t* nbr, const uint32_t* owner, const int64_t* row_ptr, uint64_t U,
@@ -706,13 +760,14 @@ static hipError_t bucket_records(const uint32_t* nbr, const uint32_t* owner, con
     uint64_t* counts = nullptr;
     unsigned long long* counters = nullptr;
     unsigned int *hubcnt = nullptr, *cursor = nullptr;
-    uint64_t *rec_off = nullptr, *task_off = nullptr, *tmp64 = nullptr;
+    uint64_t *rec_off = nullptr, *tmp64 = nullptr;
     unsigned long long hc[kCounters] = {0};
     uint64_t off_host[kBuckets + 1] = {0, 0, 0, 0, 0};
-    uint64_t ntasks = 0, total = 0;
+    uint64_t total = 0;
     const uint32_t nb = blocks_for(U ? U : 1);
     if (out->recs) (void)hipFree(out->recs);
     if (out->tasks) (void)hipFree(out->tasks);
+    if (out->fine_tasks) (void)hipFree(out->fine_tasks);
     *out = rec_set{};
     TRY(hipMallocAsync((void**)&counters, sizeof(unsigned long long) * kCounters, s));
     TRY(fill_u64((uint64_t*)counters, kCounters, 0, s));
@@ -750,54 +805,16 @@ static hipError_t bucket_records(const uint32_t* nbr, const uint32_t* owner, con
                            out->recs);
         TRY(hipGetLastError());
     }
-    // hub tasks: runs of at most `chunk` records per anchor
-    out->chunk = out->off[kBucketHub + 1] - out->off[kBucketHub] >= kHubSplitRecords ? kHubChunk / 2 : kHubChunk;
+    // hub tasks and their groups: of kHubChunk records (the set batched
+    // launches run), and for a forward-list hub bucket of kHubSplitRecords
+    // records or more also of half as many (the set a single census runs)
     if (out->off[kBucketHub + 1] > out->off[kBucketHub] && n > 0) {
-        TRY(hipMallocAsync((void**)&task_off, sizeof(uint64_t) * ((size_t)n + 1), s));
-        // two passes: anchors with rows of several LDS tiles first, then the rest
-        uint64_t part[2] = {0, 0};
-        for (int big = 1; big >= 0; --big) {
-            hipLaunchKernelGGL(k_hub_ntasks, dim3(grid1((uint64_t)n)), dim3(kT), 0, s, hubcnt, n, row_ptr, tmp64,
-                               (uint64_t)bp.hub_tile, big, out->chunk, counters);
-            TRY(hipGetLastError());
-            TRY(scan_exclusive_u64(tmp64, task_off, (uint64_t)n, task_off + n, s));
-            TRY(hipMemcpyAsync(&part[big], task_off + n, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
-            TRY(hipStreamSynchronize(s));
-        }
-        ntasks = part[1] + part[0];
-        TRY(hipMalloc((void**)&out->tasks, sizeof(hub_task) * (ntasks ? ntasks : 1)));
-        for (int big = 1; big >= 0; --big) {
-            hipLaunchKernelGGL(k_hub_ntasks, dim3(grid1((uint64_t)n)), dim3(kT), 0, s, hubcnt, n, row_ptr, tmp64,
-                               (uint64_t)bp.hub_tile, big, out->chunk, (unsigned long long*)nullptr);
-            TRY(hipGetLastError());
-            TRY(scan_exclusive_u64(tmp64, task_off, (uint64_t)n, task_off + n, s));
-            hipLaunchKernelGGL(k_hub_emit, dim3(grid1((uint64_t)n)), dim3(kT), 0, s, hubcnt, n, row_ptr, rec_off,
-                               task_off, big ? (uint64_t)0 : part[1], (uint64_t)bp.hub_tile, big, out->chunk,
-                               out->off[kBucketHub], out->tasks);
-            TRY(hipGetLastError());
-        }
-        out->n_tasks = (uint32_t)ntasks;
-        // groups of consecutive tasks
-        const uint64_t windows = (ntasks + kHubGroupTasks - 1) / kHubGroupTasks;
-        uint64_t* gcount = nullptr;
-        uint64_t ngroups = 0;
-        TRY(hipMallocAsync((void**)&gcount, sizeof(uint64_t) * (windows + 1), s));
-        hipLaunchKernelGGL(k_hub_group, dim3(grid1(windows)), dim3(kT), 0, s, out->tasks,
-                           (const dyad_rec*)out->recs, ntasks, (const uint64_t*)nullptr, gcount, bp.hub_tile,
-                           out->chunk);
-        err = hipGetLastError();
-        if (err == hipSuccess) err = scan_exclusive_u64(gcount, gcount, windows, gcount + windows, s);
-        if (err == hipSuccess) {
-            hipLaunchKernelGGL(k_hub_group, dim3(grid1(windows)), dim3(kT), 0, s, out->tasks,
-                               (const dyad_rec*)out->recs, ntasks, (const uint64_t*)gcount, (uint64_t*)nullptr,
-                               bp.hub_tile, out->chunk);
-            err = hipGetLastError();
-        }
-        if (err == hipSuccess) err = hipMemcpyAsync(&ngroups, gcount + windows, sizeof(uint64_t), hipMemcpyDeviceToHost, s);
-        if (err == hipSuccess) err = hipStreamSynchronize(s);
-        (void)hipFreeAsync(gcount, s);
-        if (err != hipSuccess) goto done;
-        out->n_groups = (uint32_t)ngroups;
+        const bool fine = tri && out->off[kBucketHub + 1] - out->off[kBucketHub] >= kHubSplitRecords;
+        TRY(cut_hub_tasks(hubcnt, n, row_ptr, rec_off, tmp64, out->off[kBucketHub], out->recs, bp, kHubChunk,
+                          counters, s, &out->tasks, &out->n_tasks, &out->n_groups));
+        if (fine)
+            TRY(cut_hub_tasks(hubcnt, n, row_ptr, rec_off, tmp64, out->off[kBucketHub], out->recs, bp, kHubChunk / 2,
+                              counters + 1, s, &out->fine_tasks, &out->fine_n_tasks, &out->fine_n_groups));
     }
     TRY(hipMemcpyAsync(hc, counters, sizeof(hc), hipMemcpyDeviceToHost, s));
     TRY(hipStreamSynchronize(s));
@@ -805,13 +822,13 @@ static hipError_t bucket_records(const uint32_t* nbr, const uint32_t* owner, con
     if (mutual) *mutual = hc[5];
     out->stream = hc[12];
     out->staged = hc[13];
+    out->fine_staged = hc[14];
 done:
     if (counts) (void)hipFreeAsync(counts, s);
     if (counters) (void)hipFreeAsync(counters, s);
     if (hubcnt) (void)hipFreeAsync(hubcnt, s);
     if (cursor) (void)hipFreeAsync(cursor, s);
     if (rec_off) (void)hipFreeAsync(rec_off, s);
-    if (task_off) (void)hipFreeAsync(task_off, s);
     if (tmp64) (void)hipFreeAsync(tmp64, s);
     (void)hipStreamSynchronize(s);
     return err;
@@ -823,6 +840,7 @@ static void free_forward(forward_lists* t) {
     if (t->fwd_ptr) (void)hipFree(t->fwd_ptr);
     if (t->edges.recs) (void)hipFree(t->edges.recs);
     if (t->edges.tasks) (void)hipFree(t->edges.tasks);
+    if (t->edges.fine_tasks) (void)hipFree(t->edges.fine_tasks);
     *t = forward_lists{};
 }
 
@@ -920,7 +938,8 @@ uint64_t device_graph_bytes(const device_graph& g) {
                  sizeof(uint64_t) + sizeof(dyad_rec) * g.p + sizeof(hub_task) * (uint64_t)g.n_hub_tasks;
     if (g.tri.fwd_ptr)
         b += sizeof(int64_t) * ((uint64_t)g.n + 1) + sizeof(uint32_t) * (2 * g.tri.entries + kRowPad) +
-             sizeof(dyad_rec) * g.tri.edges.off[kBuckets] + sizeof(hub_task) * (uint64_t)g.tri.edges.n_tasks;
+             sizeof(dyad_rec) * g.tri.edges.off[kBuckets] +
+             sizeof(hub_task) * ((uint64_t)g.tri.edges.n_tasks + g.tri.edges.fine_n_tasks);
     return b;
 }
 

@@ -1439,9 +1439,11 @@ hipError_t census_launch(const device_graph& g, const census_slices& sl, bool tr
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, counters, kBuckets * kXcds);
     const dyad_rec* recs = tri ? g.tri.edges.recs : g.dyads;
     const uint32_t* nbr = tri ? g.tri.fwd : g.nbr;
-    const hub_task* tasks = tri ? g.tri.edges.tasks : g.hub_tasks;
-    const uint32_t ntasks = tri ? g.tri.edges.n_tasks : g.n_hub_tasks;
-    const uint32_t ngroups = tri ? g.tri.edges.n_groups : g.n_hub_groups;
+    // (the forward lists' half-size hub tasks when the graph has them)
+    const bool fine = tri && g.tri.edges.fine_tasks != nullptr;
+    const hub_task* tasks = fine ? g.tri.edges.fine_tasks : tri ? g.tri.edges.tasks : g.hub_tasks;
+    const uint32_t ntasks = fine ? g.tri.edges.fine_n_tasks : tri ? g.tri.edges.n_tasks : g.n_hub_tasks;
+    const uint32_t ngroups = fine ? g.tri.edges.fine_n_groups : tri ? g.tri.edges.n_groups : g.n_hub_groups;
     const uint32_t hg0 = std::min(sl.hub_g0, ngroups), hg1 = std::max(hg0, std::min(sl.hub_g1, ngroups));
     const uint64_t te0 = std::min<uint64_t>(sl.totals_begin, g.U);
     const uint64_t te1 = std::max(te0, std::min<uint64_t>(sl.totals_end, g.U));
@@ -1475,7 +1477,7 @@ hipError_t census_launch(const device_graph& g, const census_slices& sl, bool tr
         if (ev) (void)hipEventRecord(ev[2 * b], bs);
         if (cnt > 0) {
             census_args L{recs + sl.begin[b], (uint32_t)cnt, nbr, g.tpre, (uint64_t)g.n, acc, sl.u_lo, sl.u_hi,
-                          table, tri ? g.tri.edges.chunk : g.hub_chunk};
+                          table, fine ? kHubChunk / 2 : tri ? g.tri.edges.chunk : g.hub_chunk};
             if (b == kBucketHub) {
                 L.dyads = recs;
                 if (tri) launch_hub<true>(L, tasks, ntasks, ngroups, hg0, hg1, cfg, counters, s);

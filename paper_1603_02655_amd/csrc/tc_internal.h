@@ -43,10 +43,10 @@ struct hub_task {
     uint32_t begin, end, anchor, group;
 };
 constexpr uint32_t kHubChunk = 512;           // records per hub task and per group of tasks (hub kernels' LDS)
-// A hub bucket of at least this many records is cut into tasks and groups of
-// kHubChunk / 2 records: its heavy anchors then spread over twice as many
-// workgroups (R-MAT 2^20: the hub kernel takes 7 % less time), while the
-// small graphs of a batch keep fewer, larger work items.
+// A forward-list hub bucket of at least this many records also gets tasks and
+// groups of kHubChunk / 2 records, which a single-graph census runs on the hub
+// kernel instance with the smaller LDS (R-MAT 2^20: the hub kernel takes 7 %
+// less time); batched launches keep the kHubChunk tasks (fewer, larger items).
 constexpr uint64_t kHubSplitRecords = 1ull << 20;
 constexpr uint32_t kHubTileEntries = 1024;    // anchor-row entries staged per LDS tile (default)
 constexpr uint32_t kHubGroupTasks = 8;        // consecutive hub tasks a workgroup takes at a time

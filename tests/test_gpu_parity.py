@@ -363,6 +363,12 @@ def test_full_size_identities_and_sampled_ranges(ctx, which):
         assert [int(x) for x in full] == gold["counts"]
         assert triads.identity_violations(g0.n, g0.src, g0.dst, full) == []
         assert ctx.census(g).tolist() == full.tolist()
+        # R-MAT's forward-list hub bucket holds more than 2^20 edges, so it has
+        # both hub task sets: the half-size one ran in the census above, and a
+        # batched launch runs the full-size one
+        assert g.info["tri_chunk"] == (256 if which == "rmat" else 512)
+        say(f"[gpu] batched census of {which} alone")
+        assert ctx.census_batch([g])[0].tolist() == full.tolist()
         say(f"[gpu] shards {which}")
         assert _sum_shards(ctx, g, 8)[1:].tolist() == full[1:].tolist()
         rng = np.random.default_rng(5)

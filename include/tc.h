@@ -254,8 +254,9 @@ int tc_submit(tc_context ctx, tc_graph g, tc_ticket* out);
 /* A request that carries its graph: n and m host arcs src[i] -> dst[i], copied
  * during the call.  The serving loop admits it when the build footprint fits
  * the budget, builds the graph on a serving stream, censuses it in a round and
- * frees it; a round with graphs to build is prepared on a thread of the loop's
- * own, so rounds of resident graphs keep starting meanwhile.  flags may hold
+ * frees it; a round with graphs to build holds no resident graph's request and
+ * is prepared on a thread of the loop's own, so rounds of resident graphs keep
+ * starting meanwhile.  flags may hold
  * TC_BUILD_STRICT.  Argument errors are returned at once; build errors (bad
  * ids, strict violations) by tc_poll. */
 int tc_submit_arcs(tc_context ctx, int32_t n, int64_t m, const int32_t* src, const int32_t* dst, uint32_t flags,

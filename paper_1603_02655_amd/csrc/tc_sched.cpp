@@ -156,20 +156,33 @@ void scheduler::complete_locked(job* j, int status, double t, std::vector<job*>&
 // the budget (with what is in flight and what the executor still holds); a
 // job larger than the whole budget fails with kErrNoMem.  A job that does not
 // fit yet stops the admission (no overtaking: large jobs are not starved).
+// A round holds jobs of one kind, that of the queue's first job: those whose
+// graph is built first (`builds`) or resident ones, so that a resident job
+// never waits for another job's build.  Jobs of the other kind keep their
+// place (at most max_jobs_per_round of them are passed over per round); the
+// first queued job always opens the next round.
 void scheduler::admit_locked(slot_state& s, int si, double t, std::vector<job*>& retired) {
     (void)si;
+    if (queue_.empty()) return;
     uint64_t round_entries = 0;
     const uint64_t held = ex_->held_bytes();
-    while (!queue_.empty() && s.jobs.size() < lim_.max_jobs_per_round &&
-           (s.jobs.empty() || round_entries + queue_.front()->entries <= lim_.max_round_entries)) {
-        job* j = queue_.front();
+    const bool builds = queue_.front()->builds;
+    size_t k = 0, passed = 0;
+    while (k < queue_.size() && s.jobs.size() < lim_.max_jobs_per_round) {
+        job* j = queue_[k];
+        if (j->builds != builds) {
+            if (++passed > lim_.max_jobs_per_round) break;
+            ++k;
+            continue;
+        }
+        if (!s.jobs.empty() && round_entries + j->entries > lim_.max_round_entries) break;
         if (j->footprint > lim_.budget) {
-            queue_.pop_front();
+            queue_.erase(queue_.begin() + (std::ptrdiff_t)k);
             complete_locked(j, kErrNoMem, t, retired);
             continue;
         }
         if (bytes_in_flight_ + held + j->footprint > lim_.budget) break;
-        queue_.pop_front();
+        queue_.erase(queue_.begin() + (std::ptrdiff_t)k);
         bytes_in_flight_ += j->footprint;
         round_entries += j->entries;
         j->state = kRunning;

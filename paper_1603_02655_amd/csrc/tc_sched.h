@@ -30,6 +30,7 @@ struct job {
     uint64_t ticket = 0;
     uint64_t footprint = 0;    // device bytes while the job is admitted
     uint64_t entries = 0;      // its share of a round (neighbour entries)
+    bool builds = false;       // its round builds its graph first (the request brought its arcs)
     double t_submit = 0, t_admit = 0, t_done = 0;   // ms, steady clock
     int status = kOk;
     job_state state = kQueued;

@@ -474,6 +474,7 @@ extern "C" int tc_submit_arcs(tc_context ctx, int32_t n, int64_t m, const int32_
     serve_job* j = new (std::nothrow) serve_job();
     if (!j) return TC_ERR_NOMEM;
     j->cold = true;
+    j->builds = true;   // its round runs no resident request
     j->n = n;
     j->flags = flags;
     try {

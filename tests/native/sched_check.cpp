@@ -69,6 +69,7 @@ public:
         for (job* jb : jobs) {
             fake_job* j = static_cast<fake_job*>(jb);
             CHECK(j->state == kRunning);
+            CHECK(j->builds == jobs[0]->builds);   // a round holds one kind of job
             fp += j->footprint;
             delay = std::max(delay, j->delay_ms);
             prep = std::max(prep, j->prepare_ms);
@@ -475,6 +476,70 @@ static void scenario_fifo() {
     std::printf("ok fifo\n");
 }
 
+// Rounds hold one kind of job: a resident job never shares the round of a job
+// whose graph is built first, jobs of the other kind keep their place, and the
+// first queued job opens each round.
+static void scenario_kinds() {
+    harness h(1, 1ull << 30);
+    fake_job* first = mk(0, 10);
+    first->hold = true;
+    const uint64_t t0 = h.submit(first);
+    sleep_ms(10);                          // its round holds the one slot: the rest queue up
+    std::vector<fake_job*> js;
+    std::vector<uint64_t> t;
+    for (int k = 0; k < 6; ++k) {
+        fake_job* j = mk(k + 1, 10);
+        j->builds = k % 3 == 1;            // resident, builds, resident, resident, builds, resident
+        js.push_back(j);
+        t.push_back(h.submit(j));
+    }
+    h.ex.let_go();
+    uint64_t c[16];
+    CHECK(h.wait(t0, c) == kOk);
+    std::vector<double> admit(t.size());
+    for (size_t k = 0; k < t.size(); ++k) {
+        while (!h.ex.was_done(t[k])) sleep_ms(0.05);
+        admit[k] = js[k]->t_admit;         // read before the poll retires the job
+        CHECK(h.wait(t[k], c) == kOk);
+        for (int q = 0; q < 16; ++q) CHECK(c[q] == (uint64_t)(k + 1) * 100 + (uint64_t)q);
+    }
+    // the four resident jobs in one round, then the two that build in the next
+    CHECK(admit[0] == admit[2] && admit[0] == admit[3] && admit[0] == admit[5]);
+    CHECK(admit[1] == admit[4] && admit[1] > admit[0]);
+    CHECK(h.ex.launches() == 3);
+    std::printf("ok kinds\n");
+}
+
+// The same with a job that builds at the front of the queue: it opens the
+// round (with the other job that builds), the resident jobs follow.
+static void scenario_kinds_build_first() {
+    harness h(1, 1ull << 30);
+    fake_job* first = mk(0, 10);
+    first->hold = true;
+    const uint64_t t0 = h.submit(first);
+    sleep_ms(10);
+    std::vector<fake_job*> js;
+    std::vector<uint64_t> t;
+    for (int k = 0; k < 4; ++k) {
+        fake_job* j = mk(k + 1, 10);
+        j->builds = k == 0 || k == 3;      // builds, resident, resident, builds
+        js.push_back(j);
+        t.push_back(h.submit(j));
+    }
+    h.ex.let_go();
+    uint64_t c[16];
+    CHECK(h.wait(t0, c) == kOk);
+    std::vector<double> admit(t.size());
+    for (size_t k = 0; k < t.size(); ++k) {
+        while (!h.ex.was_done(t[k])) sleep_ms(0.05);
+        admit[k] = js[k]->t_admit;
+        CHECK(h.wait(t[k], c) == kOk);
+    }
+    CHECK(admit[0] == admit[3] && admit[1] == admit[2] && admit[1] > admit[0]);
+    CHECK(h.ex.launches() == 3);
+    std::printf("ok kinds, build first\n");
+}
+
 // Cold jobs hold their bytes after they end until the executor releases them
 // (when idle, or past a quarter of the budget); admission counts them.
 static void scenario_held_bytes() {
@@ -518,6 +583,8 @@ int main() {
     scenario_busy_contract();
     scenario_stop();
     scenario_fifo();
+    scenario_kinds();
+    scenario_kinds_build_first();
     scenario_held_bytes();
     if (g_failures) {
         std::fprintf(stderr, "%d check(s) failed\n", g_failures);

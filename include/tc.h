@@ -256,7 +256,9 @@ int tc_submit(tc_context ctx, tc_graph g, tc_ticket* out);
  * the budget, builds the graph on a serving stream, censuses it in a round and
  * frees it; a round with graphs to build holds no resident graph's request and
  * is prepared on a thread of the loop's own, so rounds of resident graphs keep
- * starting meanwhile.  flags may hold
+ * starting meanwhile, and at most two of the loop's four rounds in flight
+ * build at once (a request to build waits at the front of the queue while the
+ * resident requests behind it run).  flags may hold
  * TC_BUILD_STRICT.  Argument errors are returned at once; build errors (bad
  * ids, strict violations) by tc_poll. */
 int tc_submit_arcs(tc_context ctx, int32_t n, int64_t m, const int32_t* src, const int32_t* dst, uint32_t flags,

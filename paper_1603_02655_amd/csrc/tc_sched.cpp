@@ -159,14 +159,20 @@ void scheduler::complete_locked(job* j, int status, double t, std::vector<job*>&
 // A round holds jobs of one kind, that of the queue's first job: those whose
 // graph is built first (`builds`) or resident ones, so that a resident job
 // never waits for another job's build.  Jobs of the other kind keep their
-// place (at most max_jobs_per_round of them are passed over per round); the
-// first queued job always opens the next round.
+// place (at most max_jobs_per_round of them are passed over per round).  The
+// first queued job opens the next round, unless it builds and
+// max_build_rounds rounds are building already: then the resident jobs
+// behind it run meanwhile, and it opens the round after the next build ends.
 void scheduler::admit_locked(slot_state& s, int si, double t, std::vector<job*>& retired) {
     (void)si;
     if (queue_.empty()) return;
     uint64_t round_entries = 0;
     const uint64_t held = ex_->held_bytes();
-    const bool builds = queue_.front()->builds;
+    size_t building = 0;
+    for (const slot_state& o : slots_) building += o.busy && o.builds ? 1u : 0u;
+    const bool builds = queue_.front()->builds &&
+                        (lim_.max_build_rounds == 0 || building < lim_.max_build_rounds);
+    s.builds = builds;
     size_t k = 0, passed = 0;
     while (k < queue_.size() && s.jobs.size() < lim_.max_jobs_per_round) {
         job* j = queue_[k];

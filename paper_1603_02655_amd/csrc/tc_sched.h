@@ -109,6 +109,7 @@ struct sched_limits {
     size_t max_jobs_per_round = 512;
     uint64_t max_round_entries = 64ull << 20;   // a round closes past this many entries
     double watchdog_ms = 60000.0;           // a round running longer fails its jobs
+    size_t max_build_rounds = 0;            // rounds building graphs at once (0: no limit)
 };
 
 class scheduler {
@@ -133,6 +134,7 @@ public:
 private:
     struct slot_state {
         bool busy = false, dead = false;
+        bool builds = false;   // the round's jobs build their graphs
         std::atomic<bool> finished{false};
         double t_launch = 0;
         std::vector<job*> jobs;

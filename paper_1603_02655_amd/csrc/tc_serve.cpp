@@ -383,6 +383,7 @@ serve_state* ensure_serving(tc_context_s* ctx, int* rc) {
     lim.max_jobs_per_round = kMaxJobsPerRound;
     lim.max_round_entries = kMaxRoundEntries;
     lim.watchdog_ms = ctx->watchdog_ms > 0 ? ctx->watchdog_ms : kDefaultWatchdogMs;
+    lim.max_build_rounds = kSlots / 2;   // the other slots stay free for resident graphs
     st->ex.sched = nullptr;
     try {
         st->S.reset(new sched::scheduler(&st->ex, lim));

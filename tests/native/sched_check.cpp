@@ -210,11 +210,13 @@ private:
 };
 
 struct harness {
-    harness(int slots, uint64_t budget, double watchdog_ms = 60000.0, size_t max_jobs = 512) : ex(slots, budget) {
+    harness(int slots, uint64_t budget, double watchdog_ms = 60000.0, size_t max_jobs = 512, size_t max_build = 0)
+        : ex(slots, budget) {
         sched_limits lim;
         lim.budget = budget;
         lim.watchdog_ms = watchdog_ms;
         lim.max_jobs_per_round = max_jobs;
+        lim.max_build_rounds = max_build;
         S = new scheduler(&ex, lim);
         ex.S = S;
     }
@@ -229,6 +231,17 @@ struct harness {
         const int rc = S->submit(j, &t);
         CHECK(rc == kOk);
         return t;
+    }
+    // waits until the executor has started k rounds
+    void wait_launches(int k) {
+        const double t0 = now_ms();
+        while (ex.launches() < k) {
+            if (now_ms() - t0 > 20000.0) {
+                CHECK(!"round did not start in time");
+                return;
+            }
+            sleep_ms(0.05);
+        }
     }
     // polls until done or timeout; returns the status, fills counts
     int wait(uint64_t ticket, uint64_t counts[16], double timeout_ms = 20000.0) {
@@ -484,7 +497,7 @@ static void scenario_kinds() {
     fake_job* first = mk(0, 10);
     first->hold = true;
     const uint64_t t0 = h.submit(first);
-    sleep_ms(10);                          // its round holds the one slot: the rest queue up
+    h.wait_launches(1);                    // its round holds the one slot: the rest queue up
     std::vector<fake_job*> js;
     std::vector<uint64_t> t;
     for (int k = 0; k < 6; ++k) {
@@ -517,7 +530,7 @@ static void scenario_kinds_build_first() {
     fake_job* first = mk(0, 10);
     first->hold = true;
     const uint64_t t0 = h.submit(first);
-    sleep_ms(10);
+    h.wait_launches(1);
     std::vector<fake_job*> js;
     std::vector<uint64_t> t;
     for (int k = 0; k < 4; ++k) {
@@ -538,6 +551,35 @@ static void scenario_kinds_build_first() {
     CHECK(admit[0] == admit[3] && admit[1] == admit[2] && admit[1] > admit[0]);
     CHECK(h.ex.launches() == 3);
     std::printf("ok kinds, build first\n");
+}
+
+// At most max_build_rounds rounds build at once: a job that builds waits at
+// the front while the resident jobs behind it run, and it opens the round
+// after the building one ends.
+static void scenario_build_rounds_capped() {
+    harness h(3, 1ull << 30, 60000.0, 512, 1);
+    fake_job* b1 = mk(1, 10);
+    b1->builds = true;
+    b1->hold = true;
+    const uint64_t t1 = h.submit(b1);
+    h.wait_launches(1);                    // b1's round builds on one slot
+    fake_job* b2 = mk(2, 10);
+    b2->builds = true;
+    const uint64_t t2 = h.submit(b2);
+    const uint64_t t3 = h.submit(mk(3, 10));
+    const uint64_t t4 = h.submit(mk(4, 10));
+    uint64_t c[16];
+    CHECK(h.wait(t3, c) == kOk);           // resident jobs run while b1 still builds
+    CHECK(h.wait(t4, c) == kOk);
+    CHECK(!h.ex.was_done(t1) && !h.ex.was_done(t2));
+    sleep_ms(10);
+    CHECK(!h.ex.was_done(t2));             // the one build slot is still taken
+    h.ex.let_go();
+    CHECK(h.wait(t1, c) == kOk);
+    CHECK(h.wait(t2, c) == kOk);
+    for (int q = 0; q < 16; ++q) CHECK(c[q] == 200u + (uint64_t)q);
+    CHECK(h.ex.launches() >= 3);           // (the resident jobs may have run in two rounds)
+    std::printf("ok build rounds capped\n");
 }
 
 // Cold jobs hold their bytes after they end until the executor releases them
@@ -585,6 +627,7 @@ int main() {
     scenario_fifo();
     scenario_kinds();
     scenario_kinds_build_first();
+    scenario_build_rounds_capped();
     scenario_held_bytes();
     if (g_failures) {
         std::fprintf(stderr, "%d check(s) failed\n", g_failures);

@@ -168,6 +168,65 @@ def test_single_arc_and_single_mutual(n):
     assert census(n, [(1, 2), (2, 1)]).tolist() == C(_102=n - 2, _003=comb(n, 3) - (n - 2)).tolist()
 
 
+@pytest.mark.parametrize("n", [3, 4, 5, 12])
+def test_directed_and_mutual_path(n):
+    # path 0 - 1 - ... - n-1: the n-2 consecutive triples hold two joined
+    # pairs; arc (i, i+1) with a third vertex joined to neither: n-2 choices
+    # less i-1 (when i >= 1) and i+2 (when i <= n-3), (n-2)(n-3) in all
+    path = [(i, i + 1) for i in range(n - 1)]
+    rest = comb(n, 3) - (n - 2) - (n - 2) * (n - 3)
+    assert census(n, path).tolist() == C(_021C=n - 2, _012=(n - 2) * (n - 3), _003=rest).tolist()
+    mutual = path + [(b, a) for a, b in path]
+    assert census(n, mutual).tolist() == C(_201=n - 2, _102=(n - 2) * (n - 3), _003=rest).tolist()
+
+
+@pytest.mark.parametrize("n", [3, 5, 30])
+def test_mutual_star(n):
+    arcs = [(0, i) for i in range(1, n)] + [(i, 0) for i in range(1, n)]
+    assert census(n, arcs).tolist() == C(_201=comb(n - 1, 2), _003=comb(n - 1, 3)).tolist()
+
+
+@pytest.mark.parametrize("a,b", [(1, 1), (2, 3), (4, 2), (5, 7)])
+def test_complete_bipartite(a, b):
+    # every arc from side A (0..a-1) to side B: two A vertices with one of B
+    # send both arcs to it (021U), one of A with two of B sends both (021D);
+    # with every arc mutual both mixed kinds are two mutual pairs (201)
+    A, B = range(a), range(a, a + b)
+    one_way = [(x, y) for x in A for y in B]
+    same_side = comb(a, 3) + comb(b, 3)
+    assert census(a + b, one_way).tolist() == C(_021U=comb(a, 2) * b, _021D=a * comb(b, 2), _003=same_side).tolist()
+    both = one_way + [(y, x) for x, y in one_way]
+    assert census(a + b, both).tolist() == C(_201=comb(a, 2) * b + a * comb(b, 2), _003=same_side).tolist()
+
+
+@pytest.mark.parametrize("a,b,c", [(1, 1, 1), (2, 1, 3), (3, 4, 2), (5, 2, 4)])
+def test_layered_transitive_and_chain(a, b, c):
+    # three layers A, B, C; every arc A->B and B->C, and for the transitive
+    # form also A->C.  A triple is named by how many vertices it takes from
+    # each layer.
+    A, B, Cl = range(a), range(a, a + b), range(a + b, a + b + c)
+    ab = [(x, y) for x in A for y in B]
+    bc = [(y, z) for y in B for z in Cl]
+    ac = [(x, z) for x in A for z in Cl]
+    n = a + b + c
+    same = comb(a, 3) + comb(b, 3) + comb(c, 3)
+    # transitive: one per layer is 030T; two from an earlier layer and one
+    # from a later one is 021U (both arcs into the later vertex), one from an
+    # earlier layer and two from a later one is 021D
+    exp = C(_030T=a * b * c,
+            _021U=comb(a, 2) * (b + c) + comb(b, 2) * c,
+            _021D=a * comb(b, 2) + a * comb(c, 2) + b * comb(c, 2),
+            _003=same)
+    assert census(n, ab + bc + ac).tolist() == exp.tolist()
+    # chain (no A->C arcs): one per layer is the path A->B->C (021C); A and C
+    # vertices alone are not joined (003)
+    exp = C(_021C=a * b * c,
+            _021U=comb(a, 2) * b + comb(b, 2) * c,
+            _021D=a * comb(b, 2) + b * comb(c, 2),
+            _003=same + comb(a, 2) * c + a * comb(c, 2))
+    assert census(n, ab + bc).tolist() == exp.tolist()
+
+
 @pytest.mark.parametrize("seed", range(4))
 def test_random_tournament_kendall(seed):
     rng = np.random.default_rng(seed)

@@ -82,8 +82,10 @@ typedef struct {
     uint64_t tri_groups;          /* over the hub edges of the forward lists */
     uint64_t hub_chunk;           /* records per hub task and per group, hub dyads (512) */
     uint64_t tri_chunk;           /* the same over the hub edges of the forward lists as tc_census runs
-                                     them: 256 for hub buckets of 2^20 edges or more (batched launches
-                                     run a second set of 512-record tasks), else 512 */
+                                     them: 256 for hub buckets of 2^20 edges or more, else 512; such a
+                                     bucket also holds a set of 512-record tasks over the same edges,
+                                     which batched and served launches run.  tri_tasks, tri_staged and
+                                     tri_groups describe the set tc_census runs */
 } tc_graph_info;
 
 /* Degree-bucket thresholds and launch sizes.  A dyad one of whose endpoints
